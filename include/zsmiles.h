@@ -1,0 +1,158 @@
+/*
+ * zsmiles.h - C ABI of the MI355X (gfx950) ZSMILES codec.
+ *
+ * The codec is the one of Accordi et al., "ZSMILES: an approach for efficient
+ * SMILES storage for random access in Virtual Screening": one fixed,
+ * input-independent dictionary maps printable code bytes to SMILES patterns;
+ * every line (one SMILES) is compressed on its own, so line k of the output
+ * is line k of the input and lines can be cut, combined and read at random
+ * (Sec. I).  Compression optionally renumbers ring-closure IDs first
+ * (Sec. IV-A), then takes a minimum-length parse of the line into codes and
+ * escapes (Sec. IV-D-1); decompression is a table lookup per byte
+ * (Sec. IV-D-2).
+ *
+ * Buffers.  A buffer holds lines, each ended by '\n'.  An index `off` of
+ * n+1 uint64 entries frames n lines: line k is bytes [off[k], off[k+1]-1)
+ * and byte off[k+1]-1 is its newline.  Offsets are absolute positions in the
+ * buffer, so a sub-range of lines can be passed without copying.  The last
+ * line may end at a virtual newline one past the buffer (off[n] =
+ * in_bytes + 1); that byte is never read.  Output buffers use the same
+ * framing and always start at out_off[0] = 0.
+ *
+ * Memory and streams.  Every pointer named in, out, in_off, out_off, ids,
+ * ws, res or n_lines_out is DEVICE memory owned by the caller.  Every compute
+ * call only enqueues work on `stream` (a hipStream_t passed as void*, NULL =
+ * the default stream) and returns at once; it makes no allocation and no
+ * synchronisation, so a sequence of calls can be captured into a HIP graph.
+ * The return value reports problems visible on the host (bad arguments);
+ * problems in the data are written to the device-resident zs_result `res`,
+ * valid once the stream has reached the end of the call.
+ *
+ * Errors in the data.  A line that is badly framed (ZS_EINVAL), or holds a
+ * byte outside 0x20..0x7E when compressing, or an undefined code, a dangling
+ * escape or an escaped byte outside 0x20..0x7E when decompressing
+ * (ZS_ECORRUPT), produces an empty output line; res->first_bad is the index
+ * of the first such line (request index for zs_decompress_lines) and
+ * res->code its code.  All other lines are still processed normally.  When no
+ * line is bad and the output does not fit out_cap, res->code is ZS_ENOSPC,
+ * out_off is still complete and out holds no useful bytes.
+ *
+ * Size-only mode: out == NULL computes out_off only (exact output sizes, used
+ * for admission by footprint).
+ *
+ * Workspace: `ws` is caller-owned device scratch of at least
+ * zs_workspace_bytes(op, n) bytes (n = lines, or ids for
+ * zs_decompress_lines); its contents need no initialisation.  Calls that
+ * share a workspace must not overlap in time.
+ *
+ * Thread safety: a zs_dict is immutable after creation and may be used by
+ * many streams at once.
+ */
+#ifndef ZSMILES_H
+#define ZSMILES_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    ZS_OK = 0,
+    ZS_EINVAL = -1,   /* bad argument, bad framing, id out of range, bad dictionary */
+    ZS_ENOSPC = -2,   /* output larger than out_cap (or index larger than off_cap) */
+    ZS_ECORRUPT = -3, /* data that is not a SMILES line / not a compressed line    */
+    ZS_EDEVICE = -4,  /* a HIP runtime call failed                                 */
+    ZS_ENOMEM = -5    /* host or device allocation failed (dictionary creation)    */
+} zs_status;
+
+#define ZS_LMAX_CAP 16u      /* longest expansion a dictionary may hold              */
+#define ZS_MAX_LINE 4096u    /* longest input line (bytes, newline excluded) accepted */
+#define ZS_F_PREPROCESS 0x1u /* renumber ring IDs before compressing (Sec. IV-A)      */
+
+/* Operations for zs_workspace_bytes. */
+#define ZS_OP_COMPRESS 1
+#define ZS_OP_DECOMPRESS 2
+#define ZS_OP_DECOMPRESS_LINES 3
+#define ZS_OP_INDEX 4
+
+typedef struct zs_dict zs_dict;
+
+/* Result word written by every compute call (device memory, 16 bytes). */
+typedef struct {
+    int32_t code;      /* zs_status of the data                          */
+    int32_t reserved;
+    int64_t first_bad; /* first bad line (or request) index, -1 if none  */
+} zs_result;
+
+/*
+ * Create a dictionary (Sec. IV-B, IV-C: one fixed table shared by every
+ * buffer).  len[b] is the expansion length of code byte b (0 = b is not a
+ * code); exp[b*16 .. b*16+len[b]) its expansion.  Both are HOST arrays,
+ * copied.  Rules (violations return ZS_EINVAL, *out untouched): code bytes
+ * are printable, 0x21..0x7E or 0xA1..0xFF (0x20 is the escape, 0x0A the
+ * separator); expansions are 1..16 bytes of 0x21..0x7E; no two codes share an
+ * expansion; the matcher built from the patterns must fit the on-chip budget
+ * (at most 4096 automaton states and 32 KiB of transition table).  The device
+ * copy lives on the device current at the call.  Returns ZS_EDEVICE or
+ * ZS_ENOMEM if the upload fails.
+ */
+zs_status zs_dict_create(const uint8_t *len, const uint8_t *exp, zs_dict **out);
+void zs_dict_destroy(zs_dict *d);
+/* Longest expansion of the dictionary (0 for an empty one). */
+int zs_dict_lmax(const zs_dict *d);
+
+/* Worst-case sizes, for sizing output buffers without a size-only pass. */
+uint64_t zs_compress_bound(uint64_t in_bytes, uint64_t n_lines);
+uint64_t zs_decompress_bound(const zs_dict *d, uint64_t in_bytes, uint64_t n_lines);
+/* Workspace bytes for an operation over n lines (or n ids). */
+size_t zs_workspace_bytes(int op, uint64_t n);
+
+/*
+ * Compress n_lines lines of `in` (in_bytes long, framed by in_off[0..n]).
+ * flags: ZS_F_PREPROCESS renumbers ring-closure IDs first (Sec. IV-A).  Each
+ * line is replaced by the shortest string of codes and escapes (' ' + byte)
+ * that decodes to it, the parse that takes the longest code first among the
+ * shortest ones (Sec. IV-D-1).  Output framing as described above;
+ * out_off has n_lines+1 entries.  Lines longer than ZS_MAX_LINE are bad
+ * (ZS_EINVAL).
+ */
+zs_status zs_compress(const zs_dict *d, const uint8_t *in, uint64_t in_bytes, const uint64_t *in_off,
+                      uint64_t n_lines, uint8_t *out, uint64_t out_cap, uint64_t *out_off, uint32_t flags,
+                      void *ws, size_t ws_bytes, zs_result *res, void *stream);
+
+/* Decompress every line (Sec. IV-D-2).  out_off has n_lines+1 entries. */
+zs_status zs_decompress(const zs_dict *d, const uint8_t *in, uint64_t in_bytes, const uint64_t *in_off,
+                        uint64_t n_lines, uint8_t *out, uint64_t out_cap, uint64_t *out_off, void *ws,
+                        size_t ws_bytes, zs_result *res, void *stream);
+
+/*
+ * Random access (Sec. I: separable lines): decompress lines ids[0..n_ids) of
+ * a compressed buffer and pack them in request order; out_off has n_ids+1
+ * entries.  Ids may repeat and come in any order; an id >= n_lines is a bad
+ * request (ZS_EINVAL, empty output line).
+ */
+zs_status zs_decompress_lines(const zs_dict *d, const uint8_t *in, uint64_t in_bytes, const uint64_t *in_off,
+                              uint64_t n_lines, const uint64_t *ids, uint64_t n_ids, uint8_t *out,
+                              uint64_t out_cap, uint64_t *out_off, void *ws, size_t ws_bytes, zs_result *res,
+                              void *stream);
+
+/*
+ * Build the line index of a newline-separated buffer (one SMILES per line,
+ * Sec. I): off[0] = 0, off[k+1] = one past the k-th newline; a last line
+ * without newline ends at the virtual newline len+1.  *n_lines_out (device
+ * uint64) receives the number of lines.  At most off_cap entries are written;
+ * if lines+1 > off_cap, res->code is ZS_ENOSPC.  ws: zs_workspace_bytes(
+ * ZS_OP_INDEX, len).
+ */
+zs_status zs_index_lines(const uint8_t *buf, uint64_t len, uint64_t *off, uint64_t off_cap,
+                         uint64_t *n_lines_out, void *ws, size_t ws_bytes, zs_result *res, void *stream);
+
+/* Human-readable name of a status code. */
+const char *zs_status_str(int code);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* ZSMILES_H */

@@ -496,5 +496,20 @@ int64_t zo_index_lines(const uint8_t *buf, uint64_t len, uint64_t *off, uint64_t
     return k;
 }
 
+/*
+ * Pre-process every line of a buffer (Sec. IV-A), keeping the framing:
+ * out_off[k+1] = out_off[k] + (pre-processed length of line k) + 1.  Lines are
+ * assumed well framed.  out must hold 3 * in_bytes + n bytes.
+ */
+void zo_preprocess_buffer(const uint8_t *in, const uint64_t *in_off, uint64_t n, uint8_t *out, uint64_t *out_off) {
+    out_off[0] = 0;
+    for (uint64_t k = 0; k < n; k++) {
+        int64_t xl = (int64_t)(in_off[k + 1] - in_off[k] - 1);
+        int64_t m = zo_preprocess(in + in_off[k], xl, out + out_off[k]);
+        out[out_off[k] + (uint64_t)m] = '\n';
+        out_off[k + 1] = out_off[k] + (uint64_t)m + 1;
+    }
+}
+
 /* Size helpers for callers of the library. */
 uint64_t zo_sizeof_dict(void) { return sizeof(zo_dict); }

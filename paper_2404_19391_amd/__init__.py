@@ -1,0 +1,323 @@
+"""ZSMILES codec on MI355X: Python binding of libzsmiles.so (include/zsmiles.h).
+
+Argument marshalling only: every step of compression and decompression runs in
+the HIP kernels of the library.  PyTorch provides device memory and the
+stream (torch.cuda.current_stream()); tensors are uint8 for bytes and int64
+for offsets, read as uint64 by the library.
+
+    d = Dict.load(default_dict_path())
+    c, c_off = compress(d, raw_u8, raw_off)          # Sec. IV-A + IV-D-1
+    r, r_off = decompress(d, c, c_off)               # Sec. IV-D-2
+    s, s_off = decompress_lines(d, c, c_off, ids)    # random access (Sec. I)
+
+The library must be built (python -m paper_2404_19391_amd._build); without it
+every call raises - there is no CPU fallback.
+"""
+import ctypes
+import os
+
+import numpy as np
+
+_PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_PKG, "libzsmiles.so")
+
+OK, EINVAL, ENOSPC, ECORRUPT, EDEVICE, ENOMEM = 0, -1, -2, -3, -4, -5
+F_PREPROCESS = 1
+LMAX_CAP = 16
+MAX_LINE = 4096
+OP_COMPRESS, OP_DECOMPRESS, OP_DECOMPRESS_LINES, OP_INDEX = 1, 2, 3, 4
+
+_vp = ctypes.c_void_p
+_u64 = ctypes.c_uint64
+_lib = None
+
+
+class ZsError(RuntimeError):
+    def __init__(self, code, first_bad=-1, what=""):
+        self.code = code
+        self.first_bad = first_bad
+        super().__init__("%s: %s (code %d, first bad %d)" % (what, status_str(code), code, first_bad))
+
+
+def default_dict_path():
+    return os.path.join(_PKG, "data", "default.zsd")
+
+
+def lib():
+    """The loaded libzsmiles.so; raises if it has not been built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError("libzsmiles.so is not built: run python -m paper_2404_19391_amd._build")
+        L = ctypes.CDLL(LIB_PATH)
+        L.zs_status_str.restype = ctypes.c_char_p
+        L.zs_status_str.argtypes = [ctypes.c_int]
+        L.zs_dict_create.restype = ctypes.c_int
+        L.zs_dict_create.argtypes = [_vp, _vp, ctypes.POINTER(_vp)]
+        L.zs_dict_destroy.restype = None
+        L.zs_dict_destroy.argtypes = [_vp]
+        L.zs_dict_lmax.restype = ctypes.c_int
+        L.zs_dict_lmax.argtypes = [_vp]
+        L.zs_compress_bound.restype = _u64
+        L.zs_compress_bound.argtypes = [_u64, _u64]
+        L.zs_decompress_bound.restype = _u64
+        L.zs_decompress_bound.argtypes = [_vp, _u64, _u64]
+        L.zs_workspace_bytes.restype = ctypes.c_size_t
+        L.zs_workspace_bytes.argtypes = [ctypes.c_int, _u64]
+        L.zs_compress.restype = ctypes.c_int
+        L.zs_compress.argtypes = [_vp, _vp, _u64, _vp, _u64, _vp, _u64, _vp, ctypes.c_uint32, _vp,
+                                  ctypes.c_size_t, _vp, _vp]
+        L.zs_decompress.restype = ctypes.c_int
+        L.zs_decompress.argtypes = [_vp, _vp, _u64, _vp, _u64, _vp, _u64, _vp, _vp, ctypes.c_size_t, _vp, _vp]
+        L.zs_decompress_lines.restype = ctypes.c_int
+        L.zs_decompress_lines.argtypes = [_vp, _vp, _u64, _vp, _u64, _vp, _u64, _vp, _u64, _vp, _vp,
+                                          ctypes.c_size_t, _vp, _vp]
+        L.zs_index_lines.restype = ctypes.c_int
+        L.zs_index_lines.argtypes = [_vp, _u64, _vp, _u64, _vp, _vp, ctypes.c_size_t, _vp, _vp]
+        L.zsi_compile_dict_c.restype = ctypes.c_int
+        L.zsi_compile_dict_c.argtypes = [_vp, _vp, _vp, _u64, ctypes.POINTER(_u64)]
+        _lib = L
+    return _lib
+
+
+def status_str(code):
+    try:
+        return lib().zs_status_str(int(code)).decode()
+    except RuntimeError:
+        return "status %d" % code
+
+
+def _torch():
+    import torch
+    return torch
+
+
+def _stream():
+    torch = _torch()
+    return _vp(torch.cuda.current_stream().cuda_stream)
+
+
+def _p(t):
+    return _vp(t.data_ptr()) if t is not None and t.numel() else _vp(0)
+
+
+def read_zsd(path):
+    """Parse a .zsd dictionary file: a 'ZSD1' header line, then '<hex code> <expansion>' lines."""
+    with open(path, "rb") as f:
+        rows = f.read().split(b"\n")
+    if not rows or not rows[0].startswith(b"ZSD1"):
+        raise ValueError("not a ZSD1 dictionary: %s" % path)
+    entries = {}
+    for row in rows[1:]:
+        if row:
+            code, exp = row.split(b" ", 1)
+            entries[int(code, 16)] = exp
+    return entries
+
+
+def table_arrays(entries):
+    """code -> expansion dict as the (len[256], exp[256*16]) host arrays of zs_dict_create."""
+    ln = np.zeros(256, dtype=np.uint8)
+    ex = np.zeros((256, LMAX_CAP), dtype=np.uint8)
+    for c, e in entries.items():
+        e = bytes(e)
+        if not (0 <= c < 256) or not (1 <= len(e) <= LMAX_CAP):
+            raise ZsError(EINVAL, -1, "dictionary entry %r" % (c,))
+        ln[c] = len(e)
+        ex[c, :len(e)] = np.frombuffer(e, dtype=np.uint8)
+    return ln, ex
+
+
+class Dict:
+    """A compiled dictionary resident on the current device (zs_dict)."""
+
+    def __init__(self, entries):
+        self.entries = {int(k): bytes(v) for k, v in entries.items()}
+        ln, ex = table_arrays(self.entries)
+        h = _vp()
+        rc = lib().zs_dict_create(ln.ctypes.data_as(_vp), ex.ctypes.data_as(_vp), ctypes.byref(h))
+        if rc != OK:
+            raise ZsError(rc, -1, "zs_dict_create")
+        self._h = h
+        self.lmax = lib().zs_dict_lmax(h)
+
+    @classmethod
+    def load(cls, path=None):
+        return cls(read_zsd(path or default_dict_path()))
+
+    @property
+    def handle(self):
+        return self._h
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().zs_dict_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def compile_tables(entries):
+    """Compile a dictionary into its kernel image on the host (no GPU needed); returns bytes."""
+    ln, ex = table_arrays(entries)
+    cap = 1 << 20
+    buf = np.zeros(cap, dtype=np.uint8)
+    size = _u64(0)
+    rc = lib().zsi_compile_dict_c(ln.ctypes.data_as(_vp), ex.ctypes.data_as(_vp), buf.ctypes.data_as(_vp), cap,
+                                  ctypes.byref(size))
+    if rc != OK:
+        raise ZsError(rc, -1, "compile dictionary")
+    return buf[:size.value].tobytes()
+
+
+def workspace_bytes(op, n):
+    return int(lib().zs_workspace_bytes(op, n))
+
+
+class Workspaces:
+    """Device scratch reused across calls, one per operation (calls on one stream)."""
+
+    def __init__(self, device="cuda"):
+        self.device = device
+        self._ws = {}
+
+    def get(self, op, n):
+        torch = _torch()
+        need = max(workspace_bytes(op, n), 64)
+        cur = self._ws.get(op)
+        if cur is None or cur.numel() < need:
+            cur = torch.empty(need + (need >> 3), dtype=torch.uint8, device=self.device)
+            self._ws[op] = cur
+        return cur
+
+
+_default_ws = {}
+
+
+def _ws_for(device):
+    key = str(device)
+    if key not in _default_ws:
+        _default_ws[key] = Workspaces(device)
+    return _default_ws[key]
+
+
+def new_result(device="cuda"):
+    return _torch().zeros(2, dtype=_torch().int64, device=device)
+
+
+def read_result(res):
+    v = res.cpu().numpy()
+    code = int(np.int32(v[0] & 0xFFFFFFFF))
+    return code, int(v[1])
+
+
+def _check_rc(rc, what):
+    if rc != OK:
+        raise ZsError(rc, -1, what)
+
+
+def _check_res(res, what, check):
+    code, fb = read_result(res)
+    if check and code != OK:
+        raise ZsError(code, fb, what)
+    return code, fb
+
+
+# ---- raw entry points (preallocated device buffers; enqueue only) --------------------------------
+
+def compress_into(d, buf, off, out, out_off, ws, res, preprocess=True, in_bytes=None):
+    """zs_compress on preallocated tensors; out may be None (size-only)."""
+    n = off.numel() - 1
+    nb = buf.numel() if in_bytes is None else in_bytes
+    rc = lib().zs_compress(d.handle, _p(buf), nb, _p(off), n, _p(out), out.numel() if out is not None else 0,
+                           _p(out_off), F_PREPROCESS if preprocess else 0, _p(ws), ws.numel(), _p(res), _stream())
+    _check_rc(rc, "zs_compress")
+
+
+def decompress_into(d, buf, off, out, out_off, ws, res, in_bytes=None):
+    n = off.numel() - 1
+    nb = buf.numel() if in_bytes is None else in_bytes
+    rc = lib().zs_decompress(d.handle, _p(buf), nb, _p(off), n, _p(out), out.numel() if out is not None else 0,
+                             _p(out_off), _p(ws), ws.numel(), _p(res), _stream())
+    _check_rc(rc, "zs_decompress")
+
+
+def decompress_lines_into(d, buf, off, ids, out, out_off, ws, res, in_bytes=None):
+    n = off.numel() - 1
+    nb = buf.numel() if in_bytes is None else in_bytes
+    rc = lib().zs_decompress_lines(d.handle, _p(buf), nb, _p(off), n, _p(ids), ids.numel(), _p(out),
+                                   out.numel() if out is not None else 0, _p(out_off), _p(ws), ws.numel(),
+                                   _p(res), _stream())
+    _check_rc(rc, "zs_decompress_lines")
+
+
+def index_into(buf, off, n_out, ws, res):
+    rc = lib().zs_index_lines(_p(buf), buf.numel(), _p(off), off.numel(), _p(n_out), _p(ws), ws.numel(), _p(res),
+                              _stream())
+    _check_rc(rc, "zs_index_lines")
+
+
+# ---- convenience: exact-size outputs (a size-only pass, one host read, then the call) -------------
+
+def _sized(run, out_off, device, check, what):
+    torch = _torch()
+    res = new_result(device)
+    run(None, res)
+    total = int(out_off[-1].item())
+    out = torch.empty(max(total, 1), dtype=torch.uint8, device=device)
+    res = new_result(device)
+    run(out, res)
+    _check_res(res, what, check)
+    return out[:total], out_off
+
+
+def compress(d, buf, off, preprocess=True, check=True):
+    """Compress a buffer of lines; returns (bytes uint8, offsets int64) on the same device."""
+    torch = _torch()
+    n = off.numel() - 1
+    dev = buf.device if buf.numel() else off.device
+    out_off = torch.empty(n + 1, dtype=torch.int64, device=dev)
+    ws = _ws_for(dev).get(OP_COMPRESS, n)
+    return _sized(lambda out, res: compress_into(d, buf, off, out, out_off, ws, res, preprocess), out_off, dev,
+                  check, "compress")
+
+
+def decompress(d, buf, off, check=True):
+    torch = _torch()
+    n = off.numel() - 1
+    dev = buf.device if buf.numel() else off.device
+    out_off = torch.empty(n + 1, dtype=torch.int64, device=dev)
+    ws = _ws_for(dev).get(OP_DECOMPRESS, n)
+    return _sized(lambda out, res: decompress_into(d, buf, off, out, out_off, ws, res), out_off, dev, check,
+                  "decompress")
+
+
+def decompress_lines(d, buf, off, ids, check=True):
+    torch = _torch()
+    k = ids.numel()
+    dev = off.device
+    out_off = torch.empty(k + 1, dtype=torch.int64, device=dev)
+    ws = _ws_for(dev).get(OP_DECOMPRESS_LINES, k)
+    return _sized(lambda out, res: decompress_lines_into(d, buf, off, ids, out, out_off, ws, res), out_off, dev,
+                  check, "decompress_lines")
+
+
+def index_lines(buf, check=True):
+    """Line index of a newline-separated device buffer: int64 offsets (n+1)."""
+    torch = _torch()
+    dev = buf.device
+    n_out = torch.zeros(1, dtype=torch.int64, device=dev)
+    ws = _ws_for(dev).get(OP_INDEX, buf.numel())
+    res = new_result(dev)
+    probe = torch.empty(1, dtype=torch.int64, device=dev)
+    index_into(buf, probe[:0], n_out, ws, res)  # count only
+    n = int(n_out.item())
+    off = torch.empty(n + 1, dtype=torch.int64, device=dev)
+    res = new_result(dev)
+    index_into(buf, off, n_out, ws, res)
+    _check_res(res, "index_lines", check)
+    return off

@@ -1,0 +1,217 @@
+// zs_common.hpp - device-side building blocks shared by the kernels: block
+// scans for wave64 workgroups, the single-pass decoupled look-back scan across
+// tiles, the workspace header and the result finaliser.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace zs {
+
+constexpr int kWG = 256;  // threads per workgroup in every kernel
+constexpr int kWaves = kWG / 64;
+
+// Workspace header, at the start of the caller's workspace.  Zeroed by the
+// init kernel of every call.
+struct WsHeader {
+    uint32_t ticket;   // next tile to claim
+    uint32_t done;     // workgroups that have finished
+    uint32_t enospc;   // set when the output does not fit
+    uint32_t pad0;
+    uint64_t errkey;   // min over bad lines of (index << 3 | error kind); ~0 = none
+    uint64_t total;    // total output bytes (or lines, for the index)
+    uint64_t pad[4];
+};
+static_assert(sizeof(WsHeader) == 64, "64-byte header");
+
+// Error kinds carried in the low 3 bits of errkey.
+constexpr uint32_t kErrInval = 1, kErrCorrupt = 2;
+
+__device__ inline void note_error(WsHeader* h, uint64_t index, uint32_t kind) {
+    atomicMin((unsigned long long*)&h->errkey, (unsigned long long)((index << 3) | kind));
+}
+
+// ---- decoupled look-back (Merrill & Garland, "Single-pass Parallel Prefix Scan
+//      with Decoupled Look-back", 2016).  One 64-bit word per tile: the top two
+//      bits say what the low 62 hold (1 = this tile's aggregate, 2 = inclusive
+//      prefix through this tile).
+constexpr uint64_t kFlagAgg = 1ull << 62, kFlagInc = 2ull << 62, kValMask = (1ull << 62) - 1;
+
+__device__ inline void status_store(uint64_t* p, uint64_t v) {
+    __hip_atomic_store(p, v, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ inline uint64_t status_load(uint64_t* p) {
+    return __hip_atomic_load(p, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Called by one thread of the workgroup owning tile t with its aggregate.
+// Returns the exclusive prefix (sum of all tiles before t).
+__device__ inline uint64_t lookback(uint64_t* status, uint32_t t, uint64_t agg) {
+    if (t == 0) {
+        status_store(&status[0], kFlagInc | agg);
+        return 0;
+    }
+    status_store(&status[t], kFlagAgg | agg);
+    uint64_t excl = 0;
+    int64_t j = (int64_t)t - 1;
+    while (true) {
+        uint64_t s = status_load(&status[j]);
+        uint64_t f = s & ~kValMask;
+        if (f == 0) {
+            __builtin_amdgcn_s_sleep(1);
+            continue;
+        }
+        excl += s & kValMask;
+        if (f == kFlagInc) break;
+        j--;
+    }
+    status_store(&status[t], kFlagInc | (excl + agg));
+    return excl;
+}
+
+// ---- scans over one workgroup of kWG threads (wave64)
+__device__ inline uint32_t wave_incl_scan(uint32_t v) {
+    const int lane = threadIdx.x & 63;
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+        uint32_t u = __shfl_up(v, d, 64);
+        if (lane >= d) v += u;
+    }
+    return v;
+}
+
+// Exclusive scan of v over the workgroup; *total receives the sum.
+// scratch: kWaves + 1 uint32 in LDS.  Contains barriers: call uniformly.
+__device__ inline uint32_t block_excl_scan(uint32_t v, uint32_t* scratch, uint32_t* total) {
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    uint32_t inc = wave_incl_scan(v);
+    if (lane == 63) scratch[w] = inc;
+    __syncthreads();
+    uint32_t base = 0, sum = 0;
+#pragma unroll
+    for (int k = 0; k < kWaves; k++) {
+        uint32_t s = scratch[k];
+        base += (k < w) ? s : 0;
+        sum += s;
+    }
+    __syncthreads();
+    *total = sum;
+    return base + inc - v;
+}
+
+// Same for 64-bit values.
+__device__ inline uint64_t wave_incl_scan64(uint64_t v) {
+    const int lane = threadIdx.x & 63;
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+        uint64_t u = __shfl_up(v, d, 64);
+        if (lane >= d) v += u;
+    }
+    return v;
+}
+
+__device__ inline uint64_t block_excl_scan64(uint64_t v, uint64_t* scratch, uint64_t* total) {
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    uint64_t inc = wave_incl_scan64(v);
+    if (lane == 63) scratch[w] = inc;
+    __syncthreads();
+    uint64_t base = 0, sum = 0;
+#pragma unroll
+    for (int k = 0; k < kWaves; k++) {
+        uint64_t s = scratch[k];
+        base += (k < w) ? s : 0;
+        sum += s;
+    }
+    __syncthreads();
+    *total = sum;
+    return base + inc - v;
+}
+
+// Claim the next tile: one atomic per workgroup, broadcast through LDS.
+__device__ inline uint32_t claim_tile(WsHeader* h, uint32_t* s_slot) {
+    if (threadIdx.x == 0) *s_slot = atomicAdd(&h->ticket, 1u);
+    __syncthreads();
+    uint32_t t = *s_slot;
+    __syncthreads();
+    return t;
+}
+
+// The last workgroup to finish writes the result word.  res may be null.
+struct ResultOut {
+    int32_t code;
+    int32_t reserved;
+    int64_t first_bad;
+};
+
+__device__ inline void finish_workgroup(WsHeader* h, ResultOut* res, uint32_t nblocks) {
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        __threadfence();
+        uint32_t prev = atomicAdd(&h->done, 1u);
+        if (prev == nblocks - 1) {
+            __threadfence();
+            uint64_t ek = __hip_atomic_load(&h->errkey, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
+            uint32_t nospc = __hip_atomic_load(&h->enospc, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
+            int32_t code = 0;
+            int64_t fb = -1;
+            if (ek != ~0ull) {
+                fb = (int64_t)(ek >> 3);
+                code = ((ek & 7) == kErrInval) ? -1 : -3;
+            } else if (nospc) {
+                code = -2;
+            }
+            if (res) {
+                res->code = code;
+                res->reserved = 0;
+                res->first_bad = fb;
+            }
+        }
+    }
+}
+
+// Copy bytes [glo, ghi) of an output stream from an LDS stage whose byte 0
+// corresponds to the global address a0 (a0 is 16-byte aligned, a0 <= glo).
+// Whole 16-byte chunks are written with one store, the two partial chunks at
+// the ends byte by byte, so neighbouring tiles' bytes are never touched.
+__device__ inline void flush_stage(uint8_t* out, uint64_t glo, uint64_t ghi, uintptr_t a0, const uint8_t* stage) {
+    if (ghi <= glo) return;
+    uintptr_t lo = (uintptr_t)(out + glo), hi = (uintptr_t)(out + ghi);
+    uintptr_t nchunks = (hi - a0 + 15) >> 4;
+    for (uintptr_t c = threadIdx.x; c < nchunks; c += kWG) {
+        uintptr_t ca = a0 + (c << 4);
+        const uint8_t* src = stage + (c << 4);
+        if (ca >= lo && ca + 16 <= hi) {
+            *(uint4*)ca = *(const uint4*)src;
+        } else {
+            for (int k = 0; k < 16; k++) {
+                uintptr_t p = ca + k;
+                if (p >= lo && p < hi) *(uint8_t*)p = src[k];
+            }
+        }
+    }
+}
+
+// Load global bytes [lo, hi) of `src` into an LDS buffer whose byte 0
+// corresponds to the 16-byte aligned address a0 <= src+lo.  Chunks that lie
+// fully inside [src, src+limit) are read with 16-byte loads; chunks that would
+// cross either end of the buffer are read byte by byte.
+__device__ inline void load_range(const uint8_t* src, uint64_t limit, uint64_t lo, uint64_t hi, uintptr_t a0,
+                                  uint8_t* dst) {
+    if (hi <= lo) return;
+    uintptr_t blo = (uintptr_t)src, bhi = (uintptr_t)(src + limit);
+    uintptr_t rlo = (uintptr_t)(src + lo), rhi = (uintptr_t)(src + hi);
+    uintptr_t nchunks = (rhi - a0 + 15) >> 4;
+    for (uintptr_t c = threadIdx.x; c < nchunks; c += kWG) {
+        uintptr_t ca = a0 + (c << 4);
+        uint8_t* d = dst + (c << 4);
+        if (ca >= blo && ca + 16 <= bhi) {
+            *(uint4*)d = *(const uint4*)ca;
+        } else {
+            for (int k = 0; k < 16; k++) {
+                uintptr_t p = ca + k;
+                d[k] = (p >= blo && p < bhi && p >= rlo && p < rhi) ? *(const uint8_t*)p : (uint8_t)0;
+            }
+        }
+    }
+}
+
+}  // namespace zs
