@@ -43,28 +43,44 @@ __device__ inline uint64_t status_load(uint64_t* p) {
     return __hip_atomic_load(p, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
 }
 
-// Called by one thread of the workgroup owning tile t with its aggregate.
-// Returns the exclusive prefix (sum of all tiles before t).
+__device__ inline uint64_t wave_sum64(uint64_t v) {
+#pragma unroll
+    for (int d = 32; d >= 1; d >>= 1) v += __shfl_xor(v, d, 64);
+    return v;
+}
+
+// Called by all 64 lanes of one wave of the workgroup owning tile t, with the
+// tile's aggregate.  Returns (in every lane) the exclusive prefix, the sum of
+// all tiles before t.  Each round reads the status words of the 64 closest
+// unvisited predecessors at once: the nearest one holding an inclusive prefix
+// ends the walk, the aggregates in front of it are added; a round in which a
+// nearer predecessor has not published yet is read again.
 __device__ inline uint64_t lookback(uint64_t* status, uint32_t t, uint64_t agg) {
+    const int lane = threadIdx.x & 63;
     if (t == 0) {
-        status_store(&status[0], kFlagInc | agg);
+        if (lane == 0) status_store(&status[0], kFlagInc | agg);
         return 0;
     }
-    status_store(&status[t], kFlagAgg | agg);
+    if (lane == 0) status_store(&status[t], kFlagAgg | agg);
     uint64_t excl = 0;
-    int64_t j = (int64_t)t - 1;
+    int64_t top = (int64_t)t - 1;
     while (true) {
-        uint64_t s = status_load(&status[j]);
-        uint64_t f = s & ~kValMask;
-        if (f == 0) {
+        const int64_t j = top - lane;
+        const uint64_t s = (j >= 0) ? status_load(&status[j]) : kFlagInc;
+        const uint64_t f = s & ~kValMask;
+        const uint64_t inc = __ballot(f == kFlagInc);
+        const uint64_t notready = __ballot(f == 0);
+        const int first = inc ? __builtin_ctzll(inc) : 64;
+        const uint64_t before = first >= 64 ? ~0ull : ((1ull << first) | ((1ull << first) - 1));
+        if (notready & before) {
             __builtin_amdgcn_s_sleep(1);
             continue;
         }
-        excl += s & kValMask;
-        if (f == kFlagInc) break;
-        j--;
+        excl += wave_sum64((uint64_t)lane <= (uint64_t)first ? (s & kValMask) : 0ull);
+        if (first < 64) break;
+        top -= 64;
     }
-    status_store(&status[t], kFlagInc | (excl + agg));
+    if (lane == 0) status_store(&status[t], kFlagInc | (excl + agg));
     return excl;
 }
 

@@ -39,23 +39,21 @@ namespace {
 // ============================================================================
 
 constexpr int kCL = 256;              // lines per tile (one per thread)
-constexpr int kRawCap = 14336;        // LDS bytes for the raw lines of a batch
+constexpr int kRawCap = 14336;        // LDS bytes for the raw lines of a batch; reused as output stage
 constexpr int kPreCap = 14336;        // LDS bytes for their pre-processed form
-constexpr int kTabLane = 96;          // per-lane ring tables: 16 open slots u32 + 16 last-close u16
-constexpr int kOpenSlots = 16;
-constexpr int kIdFast = 16;
+constexpr int kSlots = 8;             // fast ring tables (registers): open rings, slot = label % 8
 constexpr int kGenLane = 400;         // per-lane ring tables in global memory (any line):
                                       // 100 open positions u16 + 100 last-close u16
 static_assert(kPreCap >= 3 * (int)ZS_MAX_LINE, "a pre-processed line must fit");
 static_assert(kRawCap >= (int)ZS_MAX_LINE + 1 + 16, "a raw line must fit");
 
-constexpr int kStageCap = kRawCap + kCL * kTabLane;  // RAW + TABS, reused for output
-constexpr uint8_t kSkip = 0x7F;                      // marker: byte dropped by pre-processing
-constexpr uint8_t kIdMark = 0x80;                    // marker: ring-label with ID (low 7 bits)
+constexpr uint8_t kSkip = 0x7F;    // marker: byte dropped by pre-processing
+constexpr uint8_t kIdMark = 0x80;  // marker: ring-label with ID (low 7 bits)
+constexpr uint32_t kBadLine = 0x8000u;  // LENS flag: the line is bad (empty output)
 
 struct CompressLds {
     uint32_t tab_bytes;  // dictionary part staged
-    uint32_t raw, tabs, pre, esc, cost, eoff, off, misc;
+    uint32_t raw, pre, esc, off, cost, eoff, lens, perm, misc;
     uint32_t total;
 };
 
@@ -64,12 +62,13 @@ __host__ __device__ inline CompressLds compress_lds(uint32_t tab_bytes) {
     L.tab_bytes = align16(tab_bytes);
     uint32_t o = L.tab_bytes;
     L.raw = o;  o += kRawCap;
-    L.tabs = o; o += kCL * kTabLane;
     L.pre = o;  o += kPreCap;
     L.esc = o;  o += kPreCap / 8;
+    L.off = o;  o += align16((kCL + 1) * 8);
     L.cost = o; o += kCL * 4;
     L.eoff = o; o += kCL * 4;
-    L.off = o;  o += (kCL + 1) * 8;
+    L.lens = o; o += kCL * 2;
+    L.perm = o; o += kCL * 2;
     L.misc = o; o += 256;
     L.total = align16(o);
     return L;
@@ -93,20 +92,11 @@ struct CompressArgs {
     ResultOut* res;
 };
 
-struct Dict {
-    const TableHeader* h;
-    const uint8_t* len;
-    const uint8_t* col;
-    const uint8_t* code1;
-    const uint16_t* trans;
-    const uint32_t* outk;
-    const uint8_t* code;
-};
-
 __device__ inline bool is_digit(uint32_t c) { return c - '0' < 10u; }
 
-// Per-lane state of one line inside a batch.
+// Per-lane state of the line a lane holds inside a batch.
 struct LineState {
+    uint32_t j;     // line index inside the batch (lanes are assigned by length rank)
     uint32_t R;     // raw offset in RAW
     uint32_t len;   // raw length (newline excluded)
     uint32_t m;     // pre-processed length (0 for a bad line)
@@ -115,62 +105,53 @@ struct LineState {
     bool bad;       // framing or byte error: the output line is empty
 };
 
-// Ring-ID pass over one raw line held in RAW[R .. R+len), writing markers in
-// place.  Tables live wherever `open`/`last` point (LDS for the fast path,
-// global memory for the general one).  Returns false when the line is
-// malformed (then the caller restores it); *delta receives m - len.
-// open: nslots u32 entries, slot = value % nslots, entry ((pos+1) << 8 | value);
-// last: nid u16 entries, (position of the latest closing label with that ID) + 1.
-// *overflow is set when the tables are too small for the line.
-template <typename OpenT, typename LastT>
-__device__ inline bool ring_pass(uint8_t* raw, uint32_t R, const uint16_t* labels, uint32_t nlab, OpenT* open,
-                                 uint32_t nslots, LastT* last, uint32_t nid, int* delta, bool* overflow) {
-    int opens = 0, dl = 0;
-    for (uint32_t q = 0; q < nlab; q++) {
-        uint32_t p = labels[q];
-        uint32_t c0 = raw[R + p];
+__device__ inline void restore_line(uint8_t* raw, uint32_t R, const uint8_t* src, uint32_t len) {
+    for (uint32_t i = 0; i < len; i++) raw[R + i] = src[i];
+}
+
+// Ring IDs of one line with tables in global memory (any number of rings and
+// IDs): the rule of Sec. IV-A written as "latest close per ID": a closing ring
+// takes the smallest ID whose latest closing label precedes its opening label.
+// Markers are written over the raw line.  Returns false if the line is
+// malformed (the raw bytes are then partly overwritten and must be restored).
+__device__ inline bool ring_general(uint8_t* raw, uint32_t R, uint32_t len, uint16_t* open, uint16_t* last,
+                                    int* delta) {
+    for (int k = 0; k < 100; k++) { open[k] = 0; last[k] = 0; }
+    int dl = 0, opens = 0;
+    uint32_t inbr = 0;
+    for (uint32_t i = 0; i < len; i++) {
+        const uint32_t c = raw[R + i];
+        if (c == '[') { inbr = 1; continue; }
+        if (c == ']') { inbr = 0; continue; }
+        if (inbr) continue;
         uint32_t v, tl;
-        if (c0 == '%') {
-            v = (raw[R + p + 1] - '0') * 10u + (raw[R + p + 2] - '0');
-            tl = 3;
-        } else {
-            v = c0 - '0';
-            tl = 1;
-        }
-        uint32_t slot = v % nslots;
-        uint32_t e = open[slot];
+        if (is_digit(c)) { v = c - '0'; tl = 1; }
+        else if (c == '%') { v = (raw[R + i + 1] - '0') * 10u + (raw[R + i + 2] - '0'); tl = 3; }
+        else continue;
+        const uint32_t e = open[v];
         if (e == 0) {
-            open[slot] = ((p + 1) << 8) | v;
+            open[v] = (uint16_t)(i + 1);
             opens++;
-        } else if ((e & 0xFF) == v) {
-            uint32_t o = (e >> 8) - 1;
-            open[slot] = 0;
+        } else {
+            const uint32_t o = e - 1;
+            open[v] = 0;
             opens--;
             uint32_t id = 0;
-            while (id < nid && (uint32_t)last[id] > o + 1) id++;
-            if (id >= nid) {
-                *overflow = true;
-                return false;
-            }
-            last[id] = (LastT)(p + 1);
-            uint32_t to = (raw[R + o] == '%') ? 3u : 1u;
+            while (id < 100 && (uint32_t)last[id] > o + 1) id++;
+            if (id >= 100) return false;
+            last[id] = (uint16_t)(i + 1);
+            const uint32_t to = (raw[R + o] == '%') ? 3u : 1u;
             raw[R + o] = (uint8_t)(kIdMark | id);
             if (to == 3) raw[R + o + 1] = raw[R + o + 2] = kSkip;
-            raw[R + p] = (uint8_t)(kIdMark | id);
-            if (tl == 3) raw[R + p + 1] = raw[R + p + 2] = kSkip;
-            int nlen = id < 10 ? 1 : 3;
+            raw[R + i] = (uint8_t)(kIdMark | id);
+            if (tl == 3) raw[R + i + 1] = raw[R + i + 2] = kSkip;
+            const int nlen = id < 10 ? 1 : 3;
             dl += (nlen - (int)to) + (nlen - (int)tl);
-        } else {
-            *overflow = true;
-            return false;
         }
+        i += tl - 1;
     }
     *delta = dl;
     return opens == 0;
-}
-
-__device__ inline void restore_line(uint8_t* raw, uint32_t R, const uint8_t* src, uint32_t len) {
-    for (uint32_t i = 0; i < len; i++) raw[R + i] = src[i];
 }
 
 template <int LK>
@@ -178,24 +159,31 @@ struct Compressor {
     const CompressArgs& A;
     uint8_t* smem;
     CompressLds L;
-    Dict D;
+    const TableHeader* H;
+    const uint8_t* LENT;  // expansion lengths
+    const uint8_t* COL;
+    const uint16_t* TRANS;
+    const uint32_t* OUTK;
+    uint32_t off_code1, off_code;
     uint32_t C;  // automaton columns
 
     __device__ Compressor(const CompressArgs& a, uint8_t* s) : A(a), smem(s) {
         L = compress_lds(a.tab_bytes);
-        D.h = (const TableHeader*)smem;
-        D.len = smem + D.h->off_len;
-        D.col = smem + D.h->off_col;
-        D.code1 = smem + D.h->off_code1;
-        D.trans = (const uint16_t*)(smem + D.h->off_trans);
-        D.outk = (const uint32_t*)(smem + D.h->off_outk);
-        D.code = smem + D.h->off_code;
-        C = D.h->ncols;
+        H = (const TableHeader*)smem;
+        LENT = smem + H->off_len;
+        COL = smem + H->off_col;
+        TRANS = (const uint16_t*)(smem + H->off_trans);
+        OUTK = (const uint32_t*)(smem + H->off_outk);
+        off_code1 = H->off_code1;
+        off_code = H->off_code;
+        C = H->ncols;
     }
 
     __device__ uint64_t* OFF() { return (uint64_t*)(smem + L.off); }
     __device__ uint32_t* COST() { return (uint32_t*)(smem + L.cost); }
     __device__ uint32_t* EOFF() { return (uint32_t*)(smem + L.eoff); }
+    __device__ uint16_t* LENS() { return (uint16_t*)(smem + L.lens); }
+    __device__ uint16_t* PERM() { return (uint16_t*)(smem + L.perm); }
     __device__ uint32_t* MISC() { return (uint32_t*)(smem + L.misc); }
     __device__ uint8_t* RAW() { return smem + L.raw; }
     __device__ uint8_t* PRE() { return smem + L.pre; }
@@ -203,11 +191,136 @@ struct Compressor {
 
     // Framing of line j of the tile (OFF staged).  0 = ok, else error kind.
     __device__ uint32_t frame_error(uint64_t k0, uint32_t j) {
-        uint64_t a = OFF()[j], b = OFF()[j + 1];
+        const uint64_t a = OFF()[j], b = OFF()[j + 1];
         if (b <= a || b > A.in_bytes + 1) return kErrInval;
         if (b - a - 1 > ZS_MAX_LINE) return kErrInval;
         if (b == A.in_bytes + 1 && k0 + j + 1 != A.n) return kErrInval;
         return 0;
+    }
+
+    // Forward scan of one raw line: validate bytes, track brackets, collect the
+    // ring-label positions (u16, into PRE at the line's raw offset).
+    __device__ void scan_labels(const uint8_t* raw, uint32_t R, uint32_t len, uint16_t* list, uint32_t cap,
+                                uint32_t* nlab_out, bool* corrupt_out, bool* malformed_out, bool* over_out) {
+        uint32_t inbr = 0, pct = 0, pct_pos = 0, nlab = 0;
+        bool corrupt = false, malformed = false, over = false;
+        const uint32_t end = R + len;
+        for (uint32_t w = R & ~3u; w < end; w += 4) {
+            const uint32_t word = *(const uint32_t*)(raw + w);
+#pragma unroll
+            for (int k = 0; k < 4; k++) {
+                const uint32_t x = w + k;
+                if (x >= R && x < end) {
+                    const uint32_t c = (word >> (8 * k)) & 0xFFu;
+                    const uint32_t i = x - R;
+                    const bool dig = is_digit(c);
+                    corrupt |= (c < 0x20u) | (c > 0x7Eu);
+                    bool lab = false;
+                    uint32_t lp = i;
+                    if (inbr) {
+                        malformed |= c == '[';
+                        inbr = c != ']';
+                    } else if (pct == 1) {
+                        malformed |= !dig;
+                        pct = dig ? 2u : 0u;
+                    } else if (pct == 2) {
+                        malformed |= !dig;
+                        lab = dig;
+                        lp = pct_pos;
+                        pct = 0;
+                    } else if (c == '[') {
+                        inbr = 1;
+                    } else if (c == ']') {
+                        malformed = true;
+                    } else if (dig) {
+                        lab = true;
+                    } else if (c == '%') {
+                        pct = 1;
+                        pct_pos = i;
+                    }
+                    if (lab) {
+                        if (nlab < cap) list[nlab] = (uint16_t)lp;
+                        else over = true;
+                        nlab++;
+                    }
+                }
+            }
+        }
+        malformed |= (inbr != 0) | (pct != 0);
+        *nlab_out = nlab;
+        *corrupt_out = corrupt;
+        *malformed_out = malformed;
+        *over_out = over;
+    }
+
+    // Ring IDs from the label list with register tables: kSlots open rings
+    // (slot = label % kSlots) and, per open ring, the bit set of the IDs of the
+    // rings that closed inside it; a closing ring takes the smallest ID not in
+    // its set (Sec. IV-A).  Markers are written over the raw line.  Sets
+    // *overflow when a slot collides or an ID reaches 32; returns false when
+    // rings stay open.
+    __device__ bool ring_fast(uint8_t* raw, uint32_t R, const uint16_t* list, uint32_t nlab, uint32_t maxlab,
+                              int* delta, bool* overflow) {
+        uint32_t os[kSlots], mk[kSlots];
+#pragma unroll
+        for (int k = 0; k < kSlots; k++) { os[k] = 0; mk[k] = 0; }
+        int dl = 0, opens = 0;
+        bool ovf = false;
+        for (uint32_t q = 0; q < maxlab; q++) {
+            if (q < nlab && !ovf) {
+                const uint32_t p = list[q];
+                const uint32_t c0 = raw[R + p];
+                uint32_t v, tl;
+                if (c0 == '%') {
+                    v = (raw[R + p + 1] - '0') * 10u + (raw[R + p + 2] - '0');
+                    tl = 3;
+                } else {
+                    v = c0 - '0';
+                    tl = 1;
+                }
+                const uint32_t slot = v & (kSlots - 1);
+                uint32_t e = 0, m = 0;
+#pragma unroll
+                for (int k = 0; k < kSlots; k++) {
+                    e = (slot == (uint32_t)k) ? os[k] : e;
+                    m = (slot == (uint32_t)k) ? mk[k] : m;
+                }
+                if (e == 0) {
+#pragma unroll
+                    for (int k = 0; k < kSlots; k++) {
+                        os[k] = (slot == (uint32_t)k) ? (((p + 1) << 8) | v) : os[k];
+                        mk[k] = (slot == (uint32_t)k) ? 0u : mk[k];
+                    }
+                    opens++;
+                } else if ((e & 0xFFu) == v) {
+                    const uint32_t o = (e >> 8) - 1;
+                    const uint32_t id = (uint32_t)__builtin_ctz(~m);
+                    if (m == 0xFFFFFFFFu) {
+                        ovf = true;
+                    } else {
+                        const uint32_t bit = 1u << id;
+#pragma unroll
+                        for (int k = 0; k < kSlots; k++) {
+                            os[k] = (slot == (uint32_t)k) ? 0u : os[k];
+                            mk[k] |= bit;
+                        }
+                        opens--;
+                        const uint32_t to = (raw[R + o] == '%') ? 3u : 1u;
+                        raw[R + o] = (uint8_t)(kIdMark | id);
+                        if (to == 3) raw[R + o + 1] = raw[R + o + 2] = kSkip;
+                        raw[R + p] = (uint8_t)(kIdMark | id);
+                        if (tl == 3) raw[R + p + 1] = raw[R + p + 2] = kSkip;
+                        const int nlen = id < 10 ? 1 : 3;
+                        dl += (nlen - (int)to) + (nlen - (int)tl);
+                    }
+                } else {
+                    ovf = true;
+                }
+            }
+        }
+        *delta = dl;
+        *overflow = ovf;
+        return opens == 0;
     }
 
     // Process lines [b0, ...) of the tile as one batch: load, ring IDs, expand,
@@ -216,213 +329,148 @@ struct Compressor {
     __device__ uint32_t batch(uint64_t k0, uint32_t nl, uint32_t b0, bool regular, LineState& st) {
         uint32_t* misc = MISC();
         uint64_t* off = OFF();
+        uint16_t* lens = LENS();
+        uint16_t* perm = PERM();
+        uint8_t* raw = RAW();
+        uint8_t* pre = PRE();
         const uint32_t tid = threadIdx.x;
+        const bool prep = (A.flags & ZS_F_PREPROCESS) != 0;
         // ---- extent of the batch
         if (tid == 0) misc[0] = nl;
         __syncthreads();
         {
-            uint32_t j = b0 + tid;
-            if (j < nl) {
-                bool stop;
-                if (!regular) {
-                    stop = j > b0;  // irregular tile: one line per batch
-                } else {
-                    uint64_t lo = off[b0];
-                    stop = (off[j + 1] - lo) + 16 > (uint64_t)kRawCap;
-                    if (j == b0) stop = false;
-                }
+            const uint32_t j = b0 + tid;
+            if (j < nl && j > b0) {
+                const bool stop = !regular || (off[j + 1] - off[b0]) + 16 > (uint64_t)kRawCap;
                 if (stop) atomicMin(&misc[0], j);
             }
         }
         __syncthreads();
         uint32_t b1 = misc[0];
         __syncthreads();
-        // ---- load
-        const uint32_t fe0 = frame_error(k0, b0);
-        uint64_t lo = off[b0];
-        uint64_t hi = off[b1];
-        if (hi > A.in_bytes) hi = A.in_bytes;
-        uintptr_t a0 = ((uintptr_t)(A.in + lo)) & ~(uintptr_t)15;
-        uint32_t base_off = (uint32_t)((uintptr_t)(A.in + lo) - a0);
-        uint8_t* raw = RAW();
-        if (fe0 == 0) load_range(A.in, A.in_bytes, lo, hi, a0, raw);
-        __syncthreads();
-        if (tid == 0 && fe0 == 0 && off[b1] == A.in_bytes + 1) raw[(uint32_t)(off[b1] - 1 - lo) + base_off] = '\n';
-        // clear this lane's fast ring tables
-        {
-            uint4* t4 = (uint4*)(smem + L.tabs + tid * kTabLane);
+        while (true) {
+            const uint32_t nb = b1 - b0;
+            // ---- load
+            const uint32_t fe0 = frame_error(k0, b0);
+            const uint64_t lo = off[b0];
+            uint64_t hi = off[b1];
+            if (hi > A.in_bytes) hi = A.in_bytes;
+            const uintptr_t a0 = ((uintptr_t)(A.in + lo)) & ~(uintptr_t)15;
+            const uint32_t base_off = (uint32_t)((uintptr_t)(A.in + lo) - a0);
+            if (fe0 == 0) load_range(A.in, A.in_bytes, lo, hi, a0, raw);
+            __syncthreads();
+            if (tid == 0 && fe0 == 0 && off[b1] == A.in_bytes + 1)
+                raw[(uint32_t)(off[b1] - 1 - lo) + base_off] = '\n';
+            __syncthreads();
+            // ---- framing per line, lengths for the rank order
+            if (tid < nb) {
+                const uint32_t j = b0 + tid;
+                uint32_t fe = frame_error(k0, j);
+                uint32_t len = 0;
+                if (fe == 0) {
+                    len = (uint32_t)(off[j + 1] - off[j] - 1);
+                    if (raw[(uint32_t)(off[j] - lo) + base_off + len] != '\n') fe = kErrInval;
+                }
+                if (fe) note_error(A.ws, k0 + j, fe);
+                lens[tid] = fe ? (uint16_t)kBadLine : (uint16_t)len;
+            }
+            __syncthreads();
+            // ---- rank lines by length so that a wave holds lines of similar length
+            if (tid < nb) {
+                const uint32_t me = lens[tid];
+                uint32_t rank = 0;
+                for (uint32_t i = 0; i < nb; i++) {
+                    const uint32_t o = lens[i];
+                    rank += (o < me) | ((o == me) & (i < tid));
+                }
+                perm[rank] = (uint16_t)tid;
+            }
+            __syncthreads();
+            st.in = tid < nb;
+            st.j = st.in ? perm[tid] : 0u;
+            const uint32_t lj = st.in ? lens[st.j] : 0u;
+            st.bad = st.in && (lj & kBadLine);
+            st.len = (st.in && !st.bad) ? lj : 0u;
+            st.R = st.in ? (uint32_t)(off[b0 + st.j] - lo) + base_off : 0u;
+            st.m = 0;
+            // ---- ring IDs (Sec. IV-A)
+            bool overflow = false, malformed = false, run_rings = false;
+            int delta = 0;
+            const uint32_t line = b0 + st.j;
+            uint16_t* list = (uint16_t*)pre + ((st.R + 1) >> 1);
+            uint32_t nlab = 0;
+            if (st.in && !st.bad) {
+                bool corrupt, over;
+                scan_labels(raw, st.R, st.len, list, st.len >> 1, &nlab, &corrupt, &malformed, &over);
+                if (corrupt) {
+                    st.bad = true;
+                    note_error(A.ws, k0 + line, kErrCorrupt);
+                } else if (prep && !malformed) {
+                    if (over) overflow = true;
+                    else run_rings = true;
+                }
+            }
+            // the label loop runs to the wave's longest list (all lanes take part in the max)
+            uint32_t maxlab = run_rings ? nlab : 0u;
 #pragma unroll
-            for (int k = 0; k < kTabLane / 16; k++) t4[k] = make_uint4(0, 0, 0, 0);
-        }
-        __syncthreads();
-        // ---- per line: framing, bytes, ring IDs
-        const uint32_t j = b0 + tid;
-        st.in = j < b1;
-        st.bad = false;
-        st.len = 0;
-        st.m = 0;
-        st.R = 0;
-        bool overflow = false, malformed = false;
-        int delta = 0;
-        uint16_t* pre16 = (uint16_t*)PRE();
-        uint32_t listbase = 0, nlab = 0;
-        const bool prep = (A.flags & ZS_F_PREPROCESS) != 0;
-        if (st.in) {
-            uint32_t fe = frame_error(k0, j);
-            if (fe == 0) {
-                st.len = (uint32_t)(off[j + 1] - off[j] - 1);
-                st.R = (uint32_t)(off[j] - lo) + base_off;
-                if (raw[st.R + st.len] != '\n') fe = kErrInval;
+            for (int d = 32; d >= 1; d >>= 1) maxlab = max(maxlab, (uint32_t)__shfl_xor((int)maxlab, d, 64));
+            if (run_rings) {
+                const bool ok = ring_fast(raw, st.R, list, nlab, maxlab, &delta, &overflow);
+                if (!ok && !overflow) {
+                    malformed = true;
+                    restore_line(raw, st.R, A.in + off[line], st.len);
+                }
             }
-            if (fe) {
-                st.bad = true;
-                note_error(A.ws, k0 + j, fe);
+            if (overflow) {
+                restore_line(raw, st.R, A.in + off[line], st.len);
+                uint16_t* open = (uint16_t*)(A.gen + ((uint64_t)blockIdx.x * kWG + tid) * kGenLane);
+                if (!ring_general(raw, st.R, st.len, open, open + 100, &delta)) {
+                    malformed = true;
+                    restore_line(raw, st.R, A.in + off[line], st.len);
+                }
             }
+            if (st.in && !st.bad) st.m = (prep && !malformed) ? (uint32_t)((int)st.len + delta) : st.len;
+            // ---- pack the pre-processed lines (in lane order)
+            uint32_t total;
+            st.P = block_excl_scan(st.in ? st.m : 0u, misc + 4, &total);
+            if (total <= (uint32_t)kPreCap) break;
+            // rare: growth made PRE overflow; redo with fewer lines
+            b1 = b0 + max(1u, nb / 2);
+            __syncthreads();
         }
-        if (st.in && !st.bad) {
-            // forward scan: validate bytes, brackets, collect ring labels
-            uint32_t inbr = 0, corrupt = 0;
-            listbase = (st.R + 1) >> 1;  // u16 index into PRE
-            const uint32_t cap = st.len >> 1;
-            bool list_over = false;
-            for (uint32_t i = 0; i < st.len; i++) {
-                uint32_t c = raw[st.R + i];
-                corrupt |= (c < 0x20u) | (c > 0x7Eu);
-                if (c == '[') {
-                    malformed |= inbr != 0;
-                    inbr = 1;
-                } else if (c == ']') {
-                    malformed |= inbr == 0;
-                    inbr = 0;
-                } else if (!inbr) {
-                    bool lab = false;
-                    uint32_t adv = 0;
-                    if (is_digit(c)) {
-                        lab = true;
-                    } else if (c == '%') {
-                        if (i + 2 < st.len && is_digit(raw[st.R + i + 1]) && is_digit(raw[st.R + i + 2])) {
-                            lab = true;
-                            adv = 2;
-                        } else {
-                            malformed = true;
+        // ---- expand markers into PRE
+        if (st.in && !st.bad && st.m) {
+            uint32_t wpos = st.P;
+            const uint32_t end = st.R + st.len;
+            for (uint32_t w = st.R & ~3u; w < end; w += 4) {
+                const uint32_t word = *(const uint32_t*)(raw + w);
+#pragma unroll
+                for (int k = 0; k < 4; k++) {
+                    const uint32_t x = w + k;
+                    if (x >= st.R && x < end) {
+                        const uint32_t c = (word >> (8 * k)) & 0xFFu;
+                        if (c < kSkip) {
+                            pre[wpos++] = (uint8_t)c;
+                        } else if (c >= kIdMark) {
+                            const uint32_t id = c & 0x7F;
+                            if (id < 10) {
+                                pre[wpos++] = (uint8_t)('0' + id);
+                            } else {
+                                pre[wpos++] = '%';
+                                pre[wpos++] = (uint8_t)('0' + id / 10);
+                                pre[wpos++] = (uint8_t)('0' + id % 10);
+                            }
                         }
                     }
-                    if (lab) {
-                        if (nlab < cap) pre16[listbase + nlab] = (uint16_t)i;
-                        else list_over = true;
-                        nlab++;
-                    }
-                    i += adv;
-                }
-            }
-            malformed |= inbr != 0;
-            if (corrupt) {
-                st.bad = true;
-                note_error(A.ws, k0 + j, kErrCorrupt);
-            } else if (prep && !malformed) {
-                if (list_over) {
-                    overflow = true;
-                } else {
-                    uint32_t* open = (uint32_t*)(smem + L.tabs + tid * kTabLane);
-                    uint16_t* last = (uint16_t*)(open + kOpenSlots);
-                    bool ok = ring_pass(raw, st.R, pre16 + listbase, nlab, open, kOpenSlots, last, kIdFast, &delta,
-                                        &overflow);
-                    if (!ok && !overflow) {
-                        malformed = true;
-                        restore_line(raw, st.R, A.in + off[j], st.len);
-                    }
                 }
             }
         }
-        // ---- general path: lines whose rings do not fit the fast tables
-        if (overflow) {
-            restore_line(raw, st.R, A.in + off[j], st.len);
-            uint16_t* open = (uint16_t*)(A.gen + ((uint64_t)blockIdx.x * kWG + tid) * kGenLane);
-            uint16_t* last = open + 100;
-            for (int k = 0; k < 100; k++) { open[k] = 0; last[k] = 0; }
-            // labels again, straight from the raw bytes (the list may be incomplete)
-            int dl = 0, opens = 0;
-            bool bad_ring = false;
-            uint32_t inbr = 0;
-            for (uint32_t i = 0; i < st.len && !bad_ring; i++) {
-                uint32_t c = raw[st.R + i];
-                if (c == '[') { inbr = 1; continue; }
-                if (c == ']') { inbr = 0; continue; }
-                if (inbr) continue;
-                uint32_t v, tl;
-                if (is_digit(c)) { v = c - '0'; tl = 1; }
-                else if (c == '%') { v = (raw[st.R + i + 1] - '0') * 10u + (raw[st.R + i + 2] - '0'); tl = 3; }
-                else continue;
-                uint32_t e = open[v];
-                if (e == 0) {
-                    open[v] = (uint16_t)(i + 1);
-                    opens++;
-                } else {
-                    uint32_t o = e - 1;
-                    open[v] = 0;
-                    opens--;
-                    uint32_t id = 0;
-                    while (id < 100 && (uint32_t)last[id] > o + 1) id++;
-                    if (id >= 100) { bad_ring = true; break; }
-                    last[id] = (uint16_t)(i + 1);
-                    uint32_t to = (raw[st.R + o] == '%') ? 3u : 1u;
-                    raw[st.R + o] = (uint8_t)(kIdMark | id);
-                    if (to == 3) raw[st.R + o + 1] = raw[st.R + o + 2] = kSkip;
-                    raw[st.R + i] = (uint8_t)(kIdMark | id);
-                    if (tl == 3) raw[st.R + i + 1] = raw[st.R + i + 2] = kSkip;
-                    int nlen = id < 10 ? 1 : 3;
-                    dl += (nlen - (int)to) + (nlen - (int)tl);
-                }
-                i += tl - 1;
-            }
-            if (bad_ring || opens != 0) {
-                malformed = true;
-                restore_line(raw, st.R, A.in + off[j], st.len);
-            } else {
-                delta = dl;
-            }
-        }
-        if (st.in && !st.bad) st.m = (prep && !malformed) ? (uint32_t)((int)st.len + delta) : st.len;
-        // ---- pack the pre-processed lines; cut the batch where PRE is full
-        uint32_t total;
-        uint32_t P = block_excl_scan(st.in ? st.m : 0u, misc + 4, &total);
-        st.P = P;
-        if (tid == 0) misc[0] = b1;
-        __syncthreads();
-        if (st.in && P + st.m > (uint32_t)kPreCap) atomicMin(&misc[0], j);
-        __syncthreads();
-        uint32_t b1c = misc[0];
-        __syncthreads();
-        st.in = st.in && j < b1c;
-        b1 = b1c;
-        // ---- expand markers into PRE
-        uint8_t* pre = PRE();
-        if (st.in && !st.bad) {
-            uint32_t w = st.P;
-            for (uint32_t i = 0; i < st.len; i++) {
-                uint32_t c = raw[st.R + i];
-                if (c < kSkip) {
-                    pre[w++] = (uint8_t)c;
-                } else if (c >= kIdMark) {
-                    uint32_t id = c & 0x7F;
-                    if (id < 10) {
-                        pre[w++] = (uint8_t)('0' + id);
-                    } else {
-                        pre[w++] = '%';
-                        pre[w++] = (uint8_t)('0' + id / 10);
-                        pre[w++] = (uint8_t)('0' + id % 10);
-                    }
-                }
-            }
-        }
-        // clear the escape bits of the batch
         {
-            uint32_t words = (kPreCap + 31) / 32;
             uint32_t* esc = ESC();
-            for (uint32_t k = tid; k < words; k += kWG) esc[k] = 0;
+            for (uint32_t k = tid; k < (uint32_t)kPreCap / 32; k += kWG) esc[k] = 0;
         }
         __syncthreads();
-        // ---- parse (backward): automaton + (min,+) window
+        // ---- parse (backward): automaton + (min,+) window over the next LK costs
         uint32_t cost = 0;
         {
             const uint32_t m = (st.in && !st.bad) ? st.m : 0u;
@@ -433,46 +481,73 @@ struct Compressor {
             V[0] = 32u;
 #pragma unroll
             for (int k = 1; k < LK; k++) V[k] = 0xFFFFFFFFu;
-            uint32_t s = 0;
             uint32_t* esc = ESC();
+            uint32_t ebits = 0, eword = 0;
+            // state after the last byte, and the column of the byte before it
+            uint32_t s = 0, c = 0, coln = 0, cn = 0;
+            if (m) {
+                c = pre[st.P + m - 1];
+                s = TRANS[__umul24(0u, C) + COL[c]];
+                if (m > 1) {
+                    cn = pre[st.P + m - 2];
+                    coln = COL[cn];
+                }
+                eword = (st.P + m - 1) >> 5;
+            }
             for (uint32_t it = 0; it < mx; it++) {
                 if (it < m) {
-                    const uint32_t pos = st.P + (m - 1 - it);
-                    const uint32_t c = pre[pos];
-                    s = D.trans[s * C + D.col[c]];
-                    const uint32_t* ok = D.outk + s * LK;
-                    uint32_t K = V[0] + 63u;
-#pragma unroll
-                    for (int k = 0; k < LK; k++) K = min(K, V[k] | ok[k]);
-                    const uint32_t ch = 31u - (K & 31u);
-                    uint32_t tok;
-                    if (ch == 0) {
-                        tok = c;
-                        atomicOr(&esc[pos >> 5], 1u << (pos & 31));
-                    } else if (ch == 1) {
-                        tok = D.code1[c];
-                    } else {
-                        tok = D.code[s * LK + ch - 1];
+                    const uint32_t pos = st.P + m - 1 - it;
+                    // next state (position pos-1) and the byte after that, issued early
+                    uint32_t sn = 0, cnn = 0, colnn = 0;
+                    if (it + 1 < m) sn = TRANS[__umul24(s, C) + coln];
+                    if (it + 2 < m) {
+                        cnn = pre[pos - 2];
+                        colnn = COL[cnn];
                     }
-                    pre[pos] = (uint8_t)tok;
+                    const uint4 k0v = *(const uint4*)(OUTK + s * LK);
+                    const uint4 k1v = *(const uint4*)(OUTK + s * LK + 4);
+                    uint32_t K = V[0] + 63u;
+                    K = min(K, min(V[0] | k0v.x, V[1] | k0v.y));
+                    K = min(K, min(V[2] | k0v.z, V[3] | k0v.w));
+                    K = min(K, min(V[4] | k1v.x, V[5] | k1v.y));
+                    K = min(K, min(V[6] | k1v.z, V[7] | k1v.w));
+#pragma unroll
+                    for (int k = 8; k < LK; k += 4) {
+                        const uint4 kv = *(const uint4*)(OUTK + s * LK + k);
+                        K = min(K, min(V[k] | kv.x, V[k + 1] | kv.y));
+                        K = min(K, min(V[k + 2] | kv.z, V[k + 3] | kv.w));
+                    }
+                    const uint32_t ch = 31u - (K & 31u);
+                    const uint32_t caddr = (ch >= 2) ? (off_code + s * LK + ch - 1) : (off_code1 + c);
+                    const uint32_t t = smem[caddr];
+                    pre[pos] = (uint8_t)((ch == 0) ? c : t);
+                    if ((pos >> 5) != eword) {
+                        if (ebits) atomicOr(&esc[eword], ebits);
+                        ebits = 0;
+                        eword = pos >> 5;
+                    }
+                    ebits |= (ch == 0 ? 1u : 0u) << (pos & 31);
 #pragma unroll
                     for (int k = LK - 1; k > 0; k--) V[k] = V[k - 1];
                     V[0] = (K | 31u) + 1u;
+                    s = sn;
+                    c = cn;
+                    cn = cnn;
+                    coln = colnn;
                 }
             }
+            if (ebits) atomicOr(&esc[eword], ebits);
             cost = (V[0] >> 5) - 1u;
         }
-        if (st.in) COST()[j] = st.bad ? 0u : cost;
+        if (st.in) COST()[b0 + st.j] = st.bad ? 0u : cost;
         __syncthreads();
         return b1;
     }
 
-    // Emit the lines of the batch held in LDS into the output, windows of the
-    // stage at a time.  gbase: global output offset of the tile.
+    // Emit the lines of the batch held in LDS into the output, one stage window
+    // at a time.  gbase: global output offset of the tile.
     __device__ void emit(uint32_t b0, uint32_t b1, const LineState& st, uint64_t gbase) {
-        const uint32_t tid = threadIdx.x;
-        const uint32_t j = b0 + tid;
-        uint8_t* stage = RAW();  // RAW + TABS, both dead now
+        uint8_t* stage = RAW();  // the raw lines are dead now
         const uint8_t* pre = PRE();
         const uint32_t* esc = ESC();
         const uint64_t gb0 = gbase + EOFF()[b0];
@@ -480,10 +555,10 @@ struct Compressor {
         const uint32_t m = (st.in && !st.bad) ? st.m : 0u;
         uint32_t ic = 0;
         bool nl_done = !st.in;
-        uint64_t oc = st.in ? gbase + EOFF()[j] : 0;
+        uint64_t oc = st.in ? gbase + EOFF()[b0 + st.j] : 0;
         uint64_t wlo = gb0;
         while (wlo < gb1) {
-            uint64_t whi = wlo + (uint64_t)(kStageCap - 16);
+            uint64_t whi = wlo + (uint64_t)(kRawCap - 16);
             if (whi > gb1) whi = gb1;
             const uintptr_t a0 = ((uintptr_t)(A.out + wlo)) & ~(uintptr_t)15;
             const uintptr_t sbase = (uintptr_t)A.out - a0;  // stage index of global offset g = sbase + g
@@ -501,7 +576,7 @@ struct Compressor {
                     } else {
                         b[0] = t;
                         tl = 1;
-                        adv = D.len[t];
+                        adv = LENT[t];
                     }
                 } else {
                     b[0] = '\n';
@@ -509,7 +584,7 @@ struct Compressor {
                     adv = 0;
                 }
                 for (uint32_t k = 0; k < tl; k++) {
-                    uint64_t g = oc + k;
+                    const uint64_t g = oc + k;
                     if (g >= wlo && g < whi) stage[sbase + g] = (uint8_t)b[k];
                 }
                 if (oc + tl > whi) break;
@@ -546,12 +621,12 @@ struct Compressor {
             }
             // offsets inside the tile, then across tiles
             uint32_t total;
-            uint32_t mylen = tid < nl ? COST()[tid] + 1 : 0u;
-            uint32_t e = block_excl_scan(mylen, misc + 4, &total);
+            const uint32_t mylen = tid < nl ? COST()[tid] + 1 : 0u;
+            const uint32_t e = block_excl_scan(mylen, misc + 4, &total);
             if (tid < nl) EOFF()[tid] = e;
-            if (tid == 0) {
-                uint64_t ex = lookback(A.status, t, total);
-                ((uint64_t*)misc)[6] = ex;
+            if (tid < 64) {
+                const uint64_t ex = lookback(A.status, t, total);
+                if (tid == 0) ((uint64_t*)misc)[6] = ex;
             }
             __syncthreads();
             const uint64_t gbase = ((uint64_t*)misc)[6];
@@ -565,7 +640,7 @@ struct Compressor {
                 } else {
                     b0 = 0;
                     while (b0 < nl) {
-                        uint32_t b1 = batch(k0, nl, b0, regular, st);
+                        const uint32_t b1 = batch(k0, nl, b0, regular, st);
                         emit(b0, b1, st, gbase);
                         b0 = b1;
                     }
@@ -723,20 +798,28 @@ struct Decoder {
         const uint32_t c0 = cb_lo & ~15u;
         for (uint32_t seg = c0; seg < cb_hi; seg += kSeg) {
             const uint32_t x0 = seg + tid * 16;
-            uint8_t bytes[16];
-            if (x0 < cb_hi) *(uint4*)bytes = *(const uint4*)(cb + x0);
-            else *(uint4*)bytes = make_uint4(0, 0, 0, 0);
-            uint32_t lo = max(x0, cb_lo), hi = min(x0 + 16, cb_hi);
-            if (hi < lo) hi = lo;
-            // run info of the piece
+            uint4 w4 = make_uint4(0, 0, 0, 0);
+            if (x0 < cb_hi) w4 = *(const uint4*)(cb + x0);
+            // the 16 bytes as a 128-bit value, consumed from the low end
+            const uint64_t blo = (uint64_t)w4.x | ((uint64_t)w4.y << 32);
+            const uint64_t bhi = (uint64_t)w4.z | ((uint64_t)w4.w << 32);
+            const uint32_t lo = min(max(x0, cb_lo), x0 + 16), hi = max(min(x0 + 16, cb_hi), lo);
+            // run info of the piece [lo, hi)
             Run me = {0, 1};
-            for (uint32_t x = lo; x < hi; x++) {
-                if (bytes[x - x0] == ' ') me.run++;
-                else { me.run = 0; me.all = 0; }
+            {
+                uint64_t a = blo, b = bhi;
+                for (uint32_t x = x0; x < hi; x++) {
+                    const uint32_t c = (uint32_t)(a & 0xFF);
+                    a = (a >> 8) | (b << 56);
+                    b >>= 8;
+                    if (x >= lo) {
+                        if (c == ' ') me.run++;
+                        else { me.run = 0; me.all = 0; }
+                    }
+                }
             }
-            if (lo == hi) { me.run = 0; me.all = 1; }
             Run ex = run_scan(me, rsc);
-            uint32_t run = ex.all ? carry_run + ex.run : ex.run;
+            const uint32_t run = ex.all ? carry_run + ex.run : ex.run;
             // line of the first byte: last q with qoff[q] <= lo
             uint32_t q = b0;
             if (lo < hi) {
@@ -748,14 +831,27 @@ struct Decoder {
                 }
                 q = l;
             }
+            const uint32_t nb0 = qoff[q + 1];
+            const bool bad0 = mode == 1 && bad[q];
             // lengths
             uint32_t sum = 0;
             {
-                uint32_t rr = run, qq = q;
-                for (uint32_t x = lo; x < hi; x++) {
-                    while (x >= qoff[qq + 1]) qq++;
-                    const uint32_t c = bytes[x - x0];
-                    const bool term = x + 1 == qoff[qq + 1];
+                uint32_t rr = run, qq = q, nb = nb0;
+                bool lbad = bad0;
+                uint64_t a = blo, b = bhi;
+                for (uint32_t x = x0; x < hi; x++) {
+                    const uint32_t c = (uint32_t)(a & 0xFF);
+                    a = (a >> 8) | (b << 56);
+                    b >>= 8;
+                    if (x < lo) continue;
+                    if (x >= nb) {
+                        do {
+                            qq++;
+                            nb = qoff[qq + 1];
+                        } while (x >= nb);
+                        if (mode == 1) lbad = bad[qq];
+                    }
+                    const bool term = x + 1 == nb;
                     const bool lit = rr & 1;
                     uint32_t len;
                     bool err = false;
@@ -774,44 +870,53 @@ struct Decoder {
                     rr = (c == ' ' && !term) ? rr + 1 : 0;
                     if (mode == 0) {
                         if (err && !bad[qq]) bad[qq] = kErrCorrupt;
-                    } else if (bad[qq] && !term) {
+                    } else if (lbad && !term) {
                         len = 0;
                     }
                     sum += len;
                 }
             }
             uint32_t segtot;
-            uint32_t pos32 = block_excl_scan(sum, psc, &segtot);
-            uint64_t pos = carry_pos + pos32;
+            const uint32_t pos32 = block_excl_scan(sum, psc, &segtot);
             {
-                uint32_t rr = run, qq = q;
-                for (uint32_t x = lo; x < hi; x++) {
-                    while (x >= qoff[qq + 1]) qq++;
-                    const uint32_t c = bytes[x - x0];
-                    const bool term = x + 1 == qoff[qq + 1];
+                uint64_t pos = carry_pos + pos32;
+                uint32_t rr = run, qq = q, nb = nb0;
+                bool lbad = bad0;
+                uint64_t a = blo, b = bhi;
+                for (uint32_t x = x0; x < hi; x++) {
+                    const uint32_t c = (uint32_t)(a & 0xFF);
+                    a = (a >> 8) | (b << 56);
+                    b >>= 8;
+                    if (x < lo) continue;
+                    if (x >= nb) {
+                        do {
+                            qq++;
+                            nb = qoff[qq + 1];
+                        } while (x >= nb);
+                        if (mode == 1) lbad = bad[qq];
+                    }
+                    const bool term = x + 1 == nb;
                     const bool lit = rr & 1;
                     rr = (c == ' ' && !term) ? rr + 1 : 0;
                     if (mode == 0) {
-                        uint32_t len;
-                        if (term || lit) len = 1;
-                        else if (c == ' ') len = 0;
-                        else len = LEN[c];
+                        const uint32_t len = (term || lit) ? 1u : (c == ' ' ? 0u : (uint32_t)LEN[c]);
                         pos += len;
-                        if (term) LLEN()[qq] = (uint32_t)pos;  // end of line qq (batch-relative), fixed below
-                    } else {
-                        if (bad[qq] && !term) continue;
-                        if (term) {
-                            if (pos >= wlo && pos < whi) stage[sbase + (intptr_t)pos] = '\n';
-                            pos += 1;
-                        } else if (lit) {
-                            if (pos >= wlo && pos < whi) stage[sbase + (intptr_t)pos] = (uint8_t)c;
+                        if (term) LLEN()[qq] = (uint32_t)pos;  // end of line qq (batch-relative)
+                    } else if (!lbad || term) {
+                        if (term || lit) {
+                            if (pos >= wlo && pos < whi) stage[sbase + (intptr_t)pos] = term ? '\n' : (uint8_t)c;
                             pos += 1;
                         } else if (c != ' ') {
                             const uint32_t len = LEN[c];
                             const uint8_t* e = EXP + c * kExpStride;
-                            for (uint32_t k = 0; k < len; k++) {
-                                uint64_t p = pos + k;
-                                if (p >= wlo && p < whi) stage[sbase + (intptr_t)p] = e[k];
+                            if (pos >= wlo && pos + len <= whi) {
+                                uint8_t* d = stage + sbase + (intptr_t)pos;
+                                for (uint32_t j = 0; j < len; j++) d[j] = e[j];
+                            } else {
+                                for (uint32_t j = 0; j < len; j++) {
+                                    const uint64_t p = pos + j;
+                                    if (p >= wlo && p < whi) stage[sbase + (intptr_t)p] = e[j];
+                                }
                             }
                             pos += len;
                         }
@@ -903,7 +1008,10 @@ struct Decoder {
             const uint32_t mylen = tid < nl ? llen[tid] : 0u;
             const uint32_t e = block_excl_scan(mylen, misc + kDmScanB, &total);
             if (tid < nl) lstart[tid] = e;
-            if (tid == 0) ((uint64_t*)misc)[kDmBase64 / 2] = lookback(A.status, t, total);
+            if (tid < 64) {
+                uint64_t ex = lookback(A.status, t, total);
+                if (tid == 0) ((uint64_t*)misc)[kDmBase64 / 2] = ex;
+            }
             __syncthreads();
             const uint64_t gbase = ((uint64_t*)misc)[kDmBase64 / 2];
             if (tid < nl) A.out_off[r0 + tid + 1] = gbase + e + mylen;
@@ -987,19 +1095,41 @@ struct Decoder {
             __syncthreads();
             if (tid == 0 && lb[b1 - 1] == A.in_bytes + 1) cb[qoff[b1] - 1] = '\n';
         } else {
-            // one lane per line copies its bytes
-            if (q < b1) {
-                uint32_t p = qoff[q];
-                if (bad[q]) {
-                    cb[p] = '\n';
-                } else {
-                    const uint8_t* s = A.in + la[q];
-                    uint32_t n = (uint32_t)(lb[q] - la[q]);
-                    bool virt = lb[q] == A.in_bytes + 1;
-                    uint32_t nc = virt ? n - 1 : n;
-                    for (uint32_t k = 0; k < nc; k++) cb[p + k] = s[k];
-                    if (virt) cb[p + n - 1] = '\n';
+            // gather: each thread fills 16-byte chunks of CB; the line of a
+            // chunk's first byte comes from a search of qoff, the 16 source
+            // loads are independent so they are all in flight together
+            const uint32_t lo = qoff[b0], hi = qoff[b1];
+            for (uint32_t x0 = (lo & ~15u) + tid * 16; x0 < hi; x0 += kWG * 16) {
+                uint32_t l = b0, r = b1;
+                const uint32_t xs = max(x0, lo);
+                while (r - l > 1) {
+                    const uint32_t mid = (l + r) >> 1;
+                    if (qoff[mid] <= xs) l = mid;
+                    else r = mid;
                 }
+                uint32_t qq = l;
+                uint32_t nb = qoff[qq + 1];
+                uint8_t v[16];
+#pragma unroll
+                for (int k = 0; k < 16; k++) {
+                    const uint32_t x = x0 + k;
+                    v[k] = 0;
+                    if (x >= lo && x < hi) {
+                        while (x >= nb) {
+                            qq++;
+                            nb = qoff[qq + 1];
+                        }
+                        if (bad[qq] || (x + 1 == nb && lb[qq] == A.in_bytes + 1)) {
+                            // a bad line is a lone newline; a virtual newline is not in memory
+                            v[k] = (x + 1 == nb) ? '\n' : 0;
+                        } else {
+                            v[k] = A.in[la[qq] + (x - qoff[qq])];
+                        }
+                    }
+                }
+#pragma unroll
+                for (int k = 0; k < 16; k++)
+                    if (x0 + k >= lo && x0 + k < hi) cb[x0 + k] = v[k];
             }
             __syncthreads();
         }
@@ -1020,15 +1150,16 @@ struct Decoder {
 __global__ void __launch_bounds__(kWG) decompress_kernel(DecompressArgs a) {
     extern __shared__ __align__(16) uint8_t smem[];
     {
-        // header + LEN at [0, 320), EXP at [320, 320 + 4096)
+        // header + LEN at [0, 320), EXP at [320, 320 + 4096), in 16-byte pieces
         const TableHeader* h = (const TableHeader*)a.tables;
         const uint32_t off_len = h->off_len, off_exp = h->off_exp;
-        for (uint32_t k = threadIdx.x; k < 64 + 256 + 256 * kExpStride; k += kWG) {
-            uint8_t v;
-            if (k < 64) v = a.tables[k];
-            else if (k < 320) v = a.tables[off_len + (k - 64)];
-            else v = a.tables[off_exp + (k - 320)];
-            smem[k] = v;
+        uint4* dst = (uint4*)smem;
+        for (uint32_t k = threadIdx.x; k < (64 + 256 + 256 * kExpStride) / 16; k += kWG) {
+            uint32_t src;
+            if (k < 4) src = 16 * k;
+            else if (k < 20) src = off_len + 16 * (k - 4);
+            else src = off_exp + 16 * (k - 20);
+            dst[k] = *(const uint4*)(a.tables + src);
         }
     }
     __syncthreads();
@@ -1040,7 +1171,8 @@ __global__ void __launch_bounds__(kWG) decompress_kernel(DecompressArgs a) {
 // Line index
 // ============================================================================
 
-constexpr int kIdxTile = kWG * 64;  // bytes per tile
+constexpr int kIdxPer = 256;              // bytes per thread
+constexpr int kIdxTile = kWG * kIdxPer;    // bytes per tile
 
 struct IndexArgs {
     const uint8_t* buf;
@@ -1054,30 +1186,64 @@ struct IndexArgs {
     ResultOut* res;
 };
 
+// per 4-byte word: bit 7 of each byte set where the byte is a newline (exact,
+// no carries between bytes)
+__device__ inline uint32_t newline_bits(uint32_t w) {
+    const uint32_t x = w ^ 0x0A0A0A0Au;
+    const uint32_t nz = ((x & 0x7F7F7F7Fu) + 0x7F7F7F7Fu) | x;
+    return ~nz & 0x80808080u;
+}
+
+// 16 bytes at x, bytes past len read as spaces
+__device__ inline uint4 load16_or_pad(const uint8_t* buf, uint64_t len, uint64_t x, bool aligned) {
+    if (aligned && x + 16 <= len) return *(const uint4*)(buf + x);
+    uint32_t w[4] = {0x20202020u, 0x20202020u, 0x20202020u, 0x20202020u};
+    for (int b = 0; b < 16; b++)
+        if (x + b < len) {
+            const uint32_t sh = 8 * (b & 3);
+            w[b >> 2] = (w[b >> 2] & ~(0xFFu << sh)) | ((uint32_t)buf[x + b] << sh);
+        }
+    return make_uint4(w[0], w[1], w[2], w[3]);
+}
+
 __global__ void __launch_bounds__(kWG) index_kernel(IndexArgs a) {
     __shared__ uint64_t sc[8];
     __shared__ uint32_t slot[4];
     __shared__ uint64_t sbase;
     const uint32_t tid = threadIdx.x;
+    const bool aligned = (((uintptr_t)a.buf) & 15) == 0;
     while (true) {
         const uint32_t t = claim_tile(a.ws, &slot[0]);
         if (t >= a.ntiles) break;
-        const uint64_t x0 = (uint64_t)t * kIdxTile + (uint64_t)tid * 64;
+        const uint64_t x0 = (uint64_t)t * kIdxTile + (uint64_t)tid * kIdxPer;
         uint64_t cnt = 0;
-        for (uint32_t k = 0; k < 64; k++) {
-            uint64_t x = x0 + k;
-            if (x < a.len && a.buf[x] == '\n') cnt++;
+        for (int k = 0; k < kIdxPer / 16; k++) {
+            const uint4 v = load16_or_pad(a.buf, a.len, x0 + 16 * k, aligned);
+            cnt += __popc(newline_bits(v.x)) + __popc(newline_bits(v.y)) + __popc(newline_bits(v.z)) +
+                   __popc(newline_bits(v.w));
         }
         uint64_t tot;
         uint64_t ex = block_excl_scan64(cnt, sc, &tot);
-        if (tid == 0) sbase = lookback(a.status, t, tot);
+        if (tid < 64) {
+            uint64_t b = lookback(a.status, t, tot);
+            if (tid == 0) sbase = b;
+        }
         __syncthreads();
-        uint64_t k1 = sbase + ex;  // newlines before this thread's piece
-        for (uint32_t k = 0; k < 64; k++) {
-            uint64_t x = x0 + k;
-            if (x < a.len && a.buf[x] == '\n') {
-                k1++;
-                if (k1 < a.off_cap) a.off[k1] = x + 1;
+        uint64_t k1 = sbase + ex;  // newlines before this thread's bytes
+        if (cnt) {
+            for (int k = 0; k < kIdxPer / 16; k++) {
+                const uint4 v = load16_or_pad(a.buf, a.len, x0 + 16 * k, aligned);
+                const uint32_t wv[4] = {newline_bits(v.x), newline_bits(v.y), newline_bits(v.z), newline_bits(v.w)};
+#pragma unroll
+                for (int w = 0; w < 4; w++) {
+                    uint32_t m = wv[w];
+                    while (m) {
+                        const int bit = __builtin_ctz(m);
+                        m &= m - 1;
+                        k1++;
+                        if (k1 < a.off_cap) a.off[k1] = x0 + 16 * k + 4 * w + (bit >> 3) + 1;
+                    }
+                }
             }
         }
         if (t + 1 == a.ntiles && tid == 0) {
@@ -1158,7 +1324,7 @@ DeviceInfo device_info() {
     return cache[dev];
 }
 
-constexpr int kCompressWgPerCu = 2;
+constexpr int kCompressWgPerCu = 4;  // upper bound of the persistent grid per CU (sizes the workspace)
 constexpr int kDecompressWgPerCu = 4;
 constexpr int kIndexWgPerCu = 8;
 
@@ -1313,9 +1479,13 @@ zs_status zs_compress(const zs_dict* d, const uint8_t* in, uint64_t in_bytes, co
     a.status = status;
     a.gen = gen;
     a.res = (ResultOut*)res;
-    uint32_t grid = (uint32_t)di.cus * kCompressWgPerCu;
-    if (grid > ntiles) grid = ntiles;
     CompressLds cl = compress_lds(d->comp_bytes);
+    int occ = 0;
+    const void* kfn = d->lk == 8 ? (const void*)compress_kernel<8> : (const void*)compress_kernel<16>;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, kfn, kWG, cl.total) != hipSuccess || occ < 1) occ = 1;
+    if (occ > kCompressWgPerCu) occ = kCompressWgPerCu;
+    uint32_t grid = (uint32_t)di.cus * (uint32_t)occ;
+    if (grid > ntiles) grid = ntiles;
     if (d->lk == 8)
         hipLaunchKernelGGL(compress_kernel<8>, dim3(grid), dim3(kWG), cl.total, s, a);
     else
