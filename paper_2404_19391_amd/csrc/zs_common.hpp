@@ -49,19 +49,22 @@ __device__ inline uint64_t wave_sum64(uint64_t v) {
     return v;
 }
 
-// Called by all 64 lanes of one wave of the workgroup owning tile t, with the
-// tile's aggregate.  Returns (in every lane) the exclusive prefix, the sum of
-// all tiles before t.  Each round reads the status words of the 64 closest
-// unvisited predecessors at once: the nearest one holding an inclusive prefix
-// ends the walk, the aggregates in front of it are added; a round in which a
-// nearer predecessor has not published yet is read again.
-__device__ inline uint64_t lookback(uint64_t* status, uint32_t t, uint64_t agg) {
+// Publish a tile's aggregate (tile 0 publishes its inclusive prefix at once).
+// Called by one lane.
+__device__ inline void publish_aggregate(uint64_t* status, uint32_t t, uint64_t agg) {
+    status_store(&status[t], (t == 0 ? kFlagInc : kFlagAgg) | agg);
+}
+
+// Called by all 64 lanes of one wave of the workgroup owning tile t, whose
+// aggregate is already published.  Returns (in every lane) the exclusive
+// prefix, the sum of all tiles before t, and publishes t's inclusive prefix.
+// Each round reads the status words of the 64 closest unvisited predecessors
+// at once: the nearest one holding an inclusive prefix ends the walk, the
+// aggregates in front of it are added; a round in which a nearer predecessor
+// has not published yet is read again.
+__device__ inline uint64_t lookback_walk(uint64_t* status, uint32_t t, uint64_t agg) {
     const int lane = threadIdx.x & 63;
-    if (t == 0) {
-        if (lane == 0) status_store(&status[0], kFlagInc | agg);
-        return 0;
-    }
-    if (lane == 0) status_store(&status[t], kFlagAgg | agg);
+    if (t == 0) return 0;
     uint64_t excl = 0;
     int64_t top = (int64_t)t - 1;
     while (true) {
@@ -82,6 +85,12 @@ __device__ inline uint64_t lookback(uint64_t* status, uint32_t t, uint64_t agg) 
     }
     if (lane == 0) status_store(&status[t], kFlagInc | (excl + agg));
     return excl;
+}
+
+// Publish and walk in one go.
+__device__ inline uint64_t lookback(uint64_t* status, uint32_t t, uint64_t agg) {
+    if ((threadIdx.x & 63) == 0) publish_aggregate(status, t, agg);
+    return lookback_walk(status, t, agg);
 }
 
 // ---- scans over one workgroup of kWG threads (wave64)

@@ -89,8 +89,11 @@ struct CompressArgs {
     WsHeader* ws;
     uint64_t* status;
     uint8_t* gen;           // general ring tables, kGenLane bytes per (workgroup, lane)
+    uint8_t* slots;         // kSlotBytes per workgroup: a finished tile waiting for its offset
     ResultOut* res;
 };
+
+constexpr int kSlotBytes = kRawCap;  // a deferred tile's output fits one stage window
 
 __device__ inline bool is_digit(uint32_t c) { return c - '0' < 10u; }
 
@@ -103,6 +106,7 @@ struct LineState {
     uint32_t P;     // offset in PRE
     bool in;        // this lane holds a line of the batch
     bool bad;       // framing or byte error: the output line is empty
+    bool simple;    // batch-wide: no line changed length, tokens live in RAW, stage is PRE
 };
 
 __device__ inline void restore_line(uint8_t* raw, uint32_t R, const uint8_t* src, uint32_t len) {
@@ -198,59 +202,77 @@ struct Compressor {
         return 0;
     }
 
-    // Forward scan of one raw line: validate bytes, track brackets, collect the
-    // ring-label positions (u16, into PRE at the line's raw offset).
+    // Forward scan of one raw line, four bytes at a time with byte-parallel
+    // masks (one flag bit per byte, at bit 7 of each byte): bad bytes, bracket
+    // depth, ring labels - a digit outside brackets, or '%' outside brackets
+    // followed by two digits (Sec. II).  Label positions go to `list` (u16).
+    __device__ static inline uint32_t eq_bytes(uint32_t w, uint32_t pat) {
+        const uint32_t x = w ^ pat;
+        return ~(((x & 0x7F7F7F7Fu) + 0x7F7F7F7Fu) | x) & 0x80808080u;
+    }
     __device__ void scan_labels(const uint8_t* raw, uint32_t R, uint32_t len, uint16_t* list, uint32_t cap,
-                                uint32_t* nlab_out, bool* corrupt_out, bool* malformed_out, bool* over_out) {
-        uint32_t inbr = 0, pct = 0, pct_pos = 0, nlab = 0;
-        bool corrupt = false, malformed = false, over = false;
+                                uint32_t* nlab_out, bool* corrupt_out, bool* malformed_out, bool* over_out,
+                                bool* has_pct) {
+        uint32_t inbr = 0;      // bracket state before the current word (0 or 0x80808080-style all-ones flag)
+        uint32_t carry = 0;     // bytes of this word consumed by a '%' of the previous word (flag bits)
+        uint32_t nlab = 0;
+        uint32_t bad = 0, mal = 0, pct_any = 0;
+        bool over = false;
         const uint32_t end = R + len;
-        for (uint32_t w = R & ~3u; w < end; w += 4) {
-            const uint32_t word = *(const uint32_t*)(raw + w);
+        const uint32_t w0 = R & ~3u;
+        uint32_t word = *(const uint32_t*)(raw + w0);
+        for (uint32_t w = w0; w < end; w += 4) {
+            const uint32_t next = *(const uint32_t*)(raw + w + 4);
+            // flag bits of the bytes of this word that belong to the line
+            const uint32_t lo = R > w ? R - w : 0u, hi = end - w < 4u ? end - w : 4u;
+            const uint32_t inl = (0x80808080u << (8 * lo)) & (0x80808080u >> (8 * (4 - hi)));
+            const uint32_t nhi = end > w + 4 ? min(end - w - 4, 4u) : 0u;
+            const uint32_t inl_n = nhi ? (0x80808080u >> (8 * (4 - nhi))) : 0u;
+            // byte classes (valid only for bytes < 0x80; other bytes are corrupt anyway)
+            const uint32_t ge30 = ((word & 0x7F7F7F7Fu) + 0x50505050u) & 0x80808080u;
+            const uint32_t ge3a = ((word & 0x7F7F7F7Fu) + 0x46464646u) & 0x80808080u;
+            const uint32_t dig = ge30 & ~ge3a & ~word & inl;
+            const uint32_t ge20 = ((word & 0x7F7F7F7Fu) + 0x60606060u) & 0x80808080u;
+            bad |= ((word & 0x80808080u) | (~ge20 & 0x80808080u) | eq_bytes(word, 0x7F7F7F7Fu)) & inl;
+            const uint32_t op = eq_bytes(word, 0x5B5B5B5Bu) & inl;   // '['
+            const uint32_t cl = eq_bytes(word, 0x5D5D5D5Du) & inl;   // ']'
+            const uint32_t pc = eq_bytes(word, 0x25252525u) & inl;   // '%'
+            const uint32_t ge30n = ((next & 0x7F7F7F7Fu) + 0x50505050u) & 0x80808080u;
+            const uint32_t ge3an = ((next & 0x7F7F7F7Fu) + 0x46464646u) & 0x80808080u;
+            const uint32_t dign = ge30n & ~ge3an & ~next & inl_n;
+            // bracket state before each byte: prefix parity of the bracket bytes
+            const uint32_t br = op | cl;
+            uint32_t px = br ^ (br << 8);
+            px ^= px << 16;                      // inclusive prefix xor
+            const uint32_t inside = (px ^ br) ^ inbr;   // before each byte
+            mal |= (op & inside) | (cl & ~inside & 0x80808080u);
+            inbr = (px & 0x80000000u) ? (inbr ^ 0x80808080u) : inbr;
+            // '%' outside brackets must be followed by two digits, which it consumes
+            const uint32_t pco = pc & ~inside;
+            const uint64_t d64 = (uint64_t)dig | ((uint64_t)dign << 32);
+            const uint64_t need = ((uint64_t)pco << 8) | ((uint64_t)pco << 16);
+            mal |= (uint32_t)((need & ~d64) != 0);
+            const uint32_t consumed = (uint32_t)need | carry;
+            carry = (uint32_t)(need >> 32);
+            pct_any |= pco;
+            const uint32_t lab = ((dig & ~inside & ~consumed) | pco) & 0x80808080u;
+            if (lab) {
 #pragma unroll
-            for (int k = 0; k < 4; k++) {
-                const uint32_t x = w + k;
-                if (x >= R && x < end) {
-                    const uint32_t c = (word >> (8 * k)) & 0xFFu;
-                    const uint32_t i = x - R;
-                    const bool dig = is_digit(c);
-                    corrupt |= (c < 0x20u) | (c > 0x7Eu);
-                    bool lab = false;
-                    uint32_t lp = i;
-                    if (inbr) {
-                        malformed |= c == '[';
-                        inbr = c != ']';
-                    } else if (pct == 1) {
-                        malformed |= !dig;
-                        pct = dig ? 2u : 0u;
-                    } else if (pct == 2) {
-                        malformed |= !dig;
-                        lab = dig;
-                        lp = pct_pos;
-                        pct = 0;
-                    } else if (c == '[') {
-                        inbr = 1;
-                    } else if (c == ']') {
-                        malformed = true;
-                    } else if (dig) {
-                        lab = true;
-                    } else if (c == '%') {
-                        pct = 1;
-                        pct_pos = i;
-                    }
-                    if (lab) {
-                        if (nlab < cap) list[nlab] = (uint16_t)lp;
+                for (int k = 0; k < 4; k++) {
+                    if (lab & (0x80u << (8 * k))) {
+                        if (nlab < cap) list[nlab] = (uint16_t)(w + k - R);
                         else over = true;
                         nlab++;
                     }
                 }
             }
+            word = next;
         }
-        malformed |= (inbr != 0) | (pct != 0);
         *nlab_out = nlab;
-        *corrupt_out = corrupt;
-        *malformed_out = malformed;
+        *corrupt_out = bad != 0;
+        *malformed_out = (mal != 0) | (inbr != 0);
         *over_out = over;
+        *has_pct = pct_any != 0;
     }
 
     // Ring IDs from the label list with register tables: kSlots open rings
@@ -260,7 +282,8 @@ struct Compressor {
     // *overflow when a slot collides or an ID reaches 32; returns false when
     // rings stay open.
     __device__ bool ring_fast(uint8_t* raw, uint32_t R, const uint16_t* list, uint32_t nlab, uint32_t maxlab,
-                              int* delta, bool* overflow) {
+                              int* delta, bool* overflow, bool* marked) {
+        bool mk_any = false;
         uint32_t os[kSlots], mk[kSlots];
 #pragma unroll
         for (int k = 0; k < kSlots; k++) { os[k] = 0; mk[k] = 0; }
@@ -306,11 +329,15 @@ struct Compressor {
                         }
                         opens--;
                         const uint32_t to = (raw[R + o] == '%') ? 3u : 1u;
-                        raw[R + o] = (uint8_t)(kIdMark | id);
-                        if (to == 3) raw[R + o + 1] = raw[R + o + 2] = kSkip;
-                        raw[R + p] = (uint8_t)(kIdMark | id);
-                        if (tl == 3) raw[R + p + 1] = raw[R + p + 2] = kSkip;
                         const int nlen = id < 10 ? 1 : 3;
+                        // a one-byte label that stays one byte takes its new digit in place;
+                        // anything else is marked for the expansion pass
+                        const uint8_t nb = (nlen == 1) ? (uint8_t)('0' + id) : (uint8_t)(kIdMark | id);
+                        raw[R + o] = (to == 1) ? nb : (uint8_t)(kIdMark | id);
+                        if (to == 3) raw[R + o + 1] = raw[R + o + 2] = kSkip;
+                        raw[R + p] = (tl == 1) ? nb : (uint8_t)(kIdMark | id);
+                        if (tl == 3) raw[R + p + 1] = raw[R + p + 2] = kSkip;
+                        mk_any |= (nlen != 1) | (to != 1) | (tl != 1);
                         dl += (nlen - (int)to) + (nlen - (int)tl);
                     }
                 } else {
@@ -320,7 +347,52 @@ struct Compressor {
         }
         *delta = dl;
         *overflow = ovf;
+        *marked = mk_any;
         return opens == 0;
+    }
+
+    struct ParseState {
+        uint32_t V[LK];  // (cost + 1) << 5 of the next LK positions, in rotating slots
+        uint32_t s;      // automaton state after the current byte
+        uint32_t c;      // current byte
+        uint32_t cn, coln;  // the byte before it and its column
+    };
+
+    // Steps K.. of one unrolled group: at step K the cost of position i+L sits in
+    // slot (K - L) mod LK, and the new cost[i] replaces the oldest one, slot K.
+    template <int K>
+    __device__ __forceinline__ void parse_steps(ParseState& ps, uint8_t* buf, uint32_t base, uint32_t m,
+                                                uint32_t top) {
+        if constexpr (K < LK) {
+            const uint32_t it = base + K;
+            if (it < m) {
+                const uint32_t pos = top - it;
+                const uint32_t s = ps.s;
+                // the next state and the byte two places back are independent of the DP below
+                const uint32_t sn = TRANS[__umul24(s, C) + ps.coln];
+                const uint32_t cnn = buf[(int)pos - 2];  // may read just before the line: any byte will do
+                const uint32_t colnn = COL[cnn];
+                const uint32_t* ok = OUTK + s * LK;
+                uint32_t Kmin = ps.V[(K + LK - 1) % LK] + 63u;  // escape: cost[i+1] + 2, low bits 31
+#pragma unroll
+                for (int q = 0; q < LK; q += 4) {
+                    const uint4 kv = *(const uint4*)(ok + q);
+                    Kmin = min(Kmin, min(ps.V[(K + 2 * LK - 1 - q) % LK] | kv.x, ps.V[(K + 2 * LK - 2 - q) % LK] | kv.y));
+                    Kmin = min(Kmin, min(ps.V[(K + 2 * LK - 3 - q) % LK] | kv.z, ps.V[(K + 2 * LK - 4 - q) % LK] | kv.w));
+                }
+                const uint32_t ch = 31u - (Kmin & 31u);
+                const uint32_t caddr = (ch >= 2) ? (off_code + s * LK + ch - 1) : (off_code1 + ps.c);
+                const uint32_t t = smem[caddr];
+                buf[pos] = (uint8_t)((ch == 0) ? ps.c : t);
+                if (ch == 0) atomicOr(&ESC()[pos >> 5], 1u << (pos & 31));
+                ps.V[K] = (Kmin | 31u) + 1u;
+                ps.s = sn;
+                ps.c = ps.cn;
+                ps.cn = cnn;
+                ps.coln = colnn;
+            }
+            parse_steps<K + 1>(ps, buf, base, m, top);
+        }
     }
 
     // Process lines [b0, ...) of the tile as one batch: load, ring IDs, expand,
@@ -348,6 +420,7 @@ struct Compressor {
         __syncthreads();
         uint32_t b1 = misc[0];
         __syncthreads();
+        bool marked_lane = false;
         while (true) {
             const uint32_t nb = b1 - b0;
             // ---- load
@@ -375,15 +448,31 @@ struct Compressor {
                 lens[tid] = fe ? (uint16_t)kBadLine : (uint16_t)len;
             }
             __syncthreads();
-            // ---- rank lines by length so that a wave holds lines of similar length
-            if (tid < nb) {
-                const uint32_t me = lens[tid];
-                uint32_t rank = 0;
-                for (uint32_t i = 0; i < nb; i++) {
-                    const uint32_t o = lens[i];
-                    rank += (o < me) | ((o == me) & (i < tid));
+            // ---- rank lines by length (buckets of 8 bytes) so that a wave holds lines of
+            //      similar length; the order inside a bucket does not affect any result
+            {
+                uint32_t* cnt = ESC();  // scratch until the escape bits are cleared
+                if (tid < 64) cnt[tid] = 0;
+                __syncthreads();
+                uint32_t bk = 0, within = 0;
+                if (tid < nb) {
+                    const uint32_t lj = lens[tid];
+                    bk = (lj & kBadLine) ? 0u : min(lj >> 3, 31u);
+                    within = atomicAdd(&cnt[bk], 1u);
                 }
-                perm[rank] = (uint16_t)tid;
+                __syncthreads();
+                if (tid < 32) {
+                    const uint32_t v = cnt[tid];
+                    uint32_t inc = v;
+#pragma unroll
+                    for (int d = 1; d < 32; d <<= 1) {
+                        const uint32_t u = __shfl_up(inc, d, 64);
+                        if ((int)tid >= d) inc += u;
+                    }
+                    cnt[32 + tid] = inc - v;
+                }
+                __syncthreads();
+                if (tid < nb) perm[cnt[32 + bk] + within] = (uint16_t)tid;
             }
             __syncthreads();
             st.in = tid < nb;
@@ -400,8 +489,8 @@ struct Compressor {
             uint16_t* list = (uint16_t*)pre + ((st.R + 1) >> 1);
             uint32_t nlab = 0;
             if (st.in && !st.bad) {
-                bool corrupt, over;
-                scan_labels(raw, st.R, st.len, list, st.len >> 1, &nlab, &corrupt, &malformed, &over);
+                bool corrupt, over, pct;
+                scan_labels(raw, st.R, st.len, list, st.len >> 1, &nlab, &corrupt, &malformed, &over, &pct);
                 if (corrupt) {
                     st.bad = true;
                     note_error(A.ws, k0 + line, kErrCorrupt);
@@ -414,8 +503,9 @@ struct Compressor {
             uint32_t maxlab = run_rings ? nlab : 0u;
 #pragma unroll
             for (int d = 32; d >= 1; d >>= 1) maxlab = max(maxlab, (uint32_t)__shfl_xor((int)maxlab, d, 64));
+            bool marked = false;
             if (run_rings) {
-                const bool ok = ring_fast(raw, st.R, list, nlab, maxlab, &delta, &overflow);
+                const bool ok = ring_fast(raw, st.R, list, nlab, maxlab, &delta, &overflow, &marked);
                 if (!ok && !overflow) {
                     malformed = true;
                     restore_line(raw, st.R, A.in + off[line], st.len);
@@ -427,8 +517,12 @@ struct Compressor {
                 if (!ring_general(raw, st.R, st.len, open, open + 100, &delta)) {
                     malformed = true;
                     restore_line(raw, st.R, A.in + off[line], st.len);
+                } else {
+                    marked = true;
                 }
             }
+            if (malformed) marked = false;  // restored: the raw bytes are the line
+            marked_lane = marked;
             if (st.in && !st.bad) st.m = (prep && !malformed) ? (uint32_t)((int)st.len + delta) : st.len;
             // ---- pack the pre-processed lines (in lane order)
             uint32_t total;
@@ -438,8 +532,10 @@ struct Compressor {
             b1 = b0 + max(1u, nb / 2);
             __syncthreads();
         }
-        // ---- expand markers into PRE
-        if (st.in && !st.bad && st.m) {
+        // ---- expand markers into PRE (only when some line changed length)
+        st.simple = __syncthreads_or(st.in && !st.bad && marked_lane) == 0;
+        if (st.simple) st.P = st.R;
+        if (!st.simple && st.in && !st.bad && st.m) {
             uint32_t wpos = st.P;
             const uint32_t end = st.R + st.len;
             for (uint32_t w = st.R & ~3u; w < end; w += 4) {
@@ -473,71 +569,30 @@ struct Compressor {
         // ---- parse (backward): automaton + (min,+) window over the next LK costs
         uint32_t cost = 0;
         {
+            uint8_t* buf = st.simple ? raw : pre;
             const uint32_t m = (st.in && !st.bad) ? st.m : 0u;
             uint32_t mx = m;
 #pragma unroll
             for (int d = 32; d >= 1; d >>= 1) mx = max(mx, (uint32_t)__shfl_xor((int)mx, d, 64));
-            uint32_t V[LK];
-            V[0] = 32u;
+            ParseState ps;
 #pragma unroll
-            for (int k = 1; k < LK; k++) V[k] = 0xFFFFFFFFu;
-            uint32_t* esc = ESC();
-            uint32_t ebits = 0, eword = 0;
-            // state after the last byte, and the column of the byte before it
-            uint32_t s = 0, c = 0, coln = 0, cn = 0;
+            for (int k = 0; k < LK; k++) ps.V[k] = 0xFFFFFFFFu;
+            ps.V[LK - 1] = 32u;  // cost[m] = 0, as (cost + 1) << 5
+            const uint32_t top = st.P + m - 1;  // position of the last byte (unused when m == 0)
+            ps.c = buf[(int)top];
+            ps.s = TRANS[COL[ps.c]];
+            ps.cn = buf[(int)top - 1];
+            ps.coln = COL[ps.cn];
+            for (uint32_t base = 0; base < mx; base += LK) {
+                parse_steps<0>(ps, buf, base, m, top);
+            }
             if (m) {
-                c = pre[st.P + m - 1];
-                s = TRANS[__umul24(0u, C) + COL[c]];
-                if (m > 1) {
-                    cn = pre[st.P + m - 2];
-                    coln = COL[cn];
-                }
-                eword = (st.P + m - 1) >> 5;
-            }
-            for (uint32_t it = 0; it < mx; it++) {
-                if (it < m) {
-                    const uint32_t pos = st.P + m - 1 - it;
-                    // next state (position pos-1) and the byte after that, issued early
-                    uint32_t sn = 0, cnn = 0, colnn = 0;
-                    if (it + 1 < m) sn = TRANS[__umul24(s, C) + coln];
-                    if (it + 2 < m) {
-                        cnn = pre[pos - 2];
-                        colnn = COL[cnn];
-                    }
-                    const uint4 k0v = *(const uint4*)(OUTK + s * LK);
-                    const uint4 k1v = *(const uint4*)(OUTK + s * LK + 4);
-                    uint32_t K = V[0] + 63u;
-                    K = min(K, min(V[0] | k0v.x, V[1] | k0v.y));
-                    K = min(K, min(V[2] | k0v.z, V[3] | k0v.w));
-                    K = min(K, min(V[4] | k1v.x, V[5] | k1v.y));
-                    K = min(K, min(V[6] | k1v.z, V[7] | k1v.w));
+                const uint32_t last = (m - 1) & (LK - 1);
+                uint32_t v = 0;
 #pragma unroll
-                    for (int k = 8; k < LK; k += 4) {
-                        const uint4 kv = *(const uint4*)(OUTK + s * LK + k);
-                        K = min(K, min(V[k] | kv.x, V[k + 1] | kv.y));
-                        K = min(K, min(V[k + 2] | kv.z, V[k + 3] | kv.w));
-                    }
-                    const uint32_t ch = 31u - (K & 31u);
-                    const uint32_t caddr = (ch >= 2) ? (off_code + s * LK + ch - 1) : (off_code1 + c);
-                    const uint32_t t = smem[caddr];
-                    pre[pos] = (uint8_t)((ch == 0) ? c : t);
-                    if ((pos >> 5) != eword) {
-                        if (ebits) atomicOr(&esc[eword], ebits);
-                        ebits = 0;
-                        eword = pos >> 5;
-                    }
-                    ebits |= (ch == 0 ? 1u : 0u) << (pos & 31);
-#pragma unroll
-                    for (int k = LK - 1; k > 0; k--) V[k] = V[k - 1];
-                    V[0] = (K | 31u) + 1u;
-                    s = sn;
-                    c = cn;
-                    cn = cnn;
-                    coln = colnn;
-                }
+                for (int k = 0; k < LK; k++) v = ((uint32_t)k == last) ? ps.V[k] : v;
+                cost = (v >> 5) - 1u;
             }
-            if (ebits) atomicOr(&esc[eword], ebits);
-            cost = (V[0] >> 5) - 1u;
         }
         if (st.in) COST()[b0 + st.j] = st.bad ? 0u : cost;
         __syncthreads();
@@ -546,9 +601,11 @@ struct Compressor {
 
     // Emit the lines of the batch held in LDS into the output, one stage window
     // at a time.  gbase: global output offset of the tile.
-    __device__ void emit(uint32_t b0, uint32_t b1, const LineState& st, uint64_t gbase) {
-        uint8_t* stage = RAW();  // the raw lines are dead now
-        const uint8_t* pre = PRE();
+    // rel: write the batch at tile-relative offsets from stage byte 0 and leave it
+    // there (one window; the caller copies it out later).
+    __device__ void emit(uint32_t b0, uint32_t b1, const LineState& st, uint64_t gbase, bool rel = false) {
+        uint8_t* stage = st.simple ? PRE() : RAW();        // the buffer not holding tokens
+        const uint8_t* pre = st.simple ? RAW() : PRE();
         const uint32_t* esc = ESC();
         const uint64_t gb0 = gbase + EOFF()[b0];
         const uint64_t gb1 = gbase + EOFF()[b1 - 1] + COST()[b1 - 1] + 1;
@@ -558,10 +615,10 @@ struct Compressor {
         uint64_t oc = st.in ? gbase + EOFF()[b0 + st.j] : 0;
         uint64_t wlo = gb0;
         while (wlo < gb1) {
-            uint64_t whi = wlo + (uint64_t)(kRawCap - 16);
+            uint64_t whi = wlo + (uint64_t)(min(kRawCap, kPreCap) - 16);
             if (whi > gb1) whi = gb1;
-            const uintptr_t a0 = ((uintptr_t)(A.out + wlo)) & ~(uintptr_t)15;
-            const uintptr_t sbase = (uintptr_t)A.out - a0;  // stage index of global offset g = sbase + g
+            const uintptr_t a0 = rel ? 0 : (((uintptr_t)(A.out + wlo)) & ~(uintptr_t)15);
+            const uintptr_t sbase = rel ? 0 : (uintptr_t)A.out - a0;  // stage index of offset g = sbase + g
             while (!nl_done && oc < whi) {
                 uint32_t b[2];
                 uint32_t tl, adv;
@@ -593,56 +650,124 @@ struct Compressor {
                 else nl_done = true;
             }
             __syncthreads();
-            flush_stage(A.out, wlo, whi, a0, stage);
+            if (!rel) flush_stage(A.out, wlo, whi, a0, stage);
             __syncthreads();
             wlo = whi;
         }
     }
 
+    // Copy a deferred tile's bytes from its global slot to out[base, base+total),
+    // through an LDS stage shifted to the destination's 16-byte alignment.
+    __device__ void copy_slot(const uint8_t* slot, uint32_t total, uint64_t base, uint8_t* stage) {
+        const uintptr_t dst = (uintptr_t)(A.out + base);
+        const uint32_t shift = (uint32_t)(dst & 15);
+        const uint32_t nch = (total + 15) / 16;
+        for (uint32_t c = threadIdx.x; c < nch; c += kWG) {
+            const uint4 v = *(const uint4*)(slot + 16 * c);
+            const uint32_t w[4] = {v.x, v.y, v.z, v.w};
+#pragma unroll
+            for (int k = 0; k < 16; k++) {
+                if (16 * c + k < total) stage[shift + 16 * c + k] = (uint8_t)(w[k >> 2] >> (8 * (k & 3)));
+            }
+        }
+        __syncthreads();
+        flush_stage(A.out, base, base + total, dst - shift, stage);
+        __syncthreads();
+    }
+
+    // Tiles are processed in ticket order.  A tile whose output fits one stage
+    // window publishes its size as soon as it is parsed, parks its bytes in this
+    // workgroup's global slot and is placed one tile later, when its
+    // predecessors have published: no workgroup waits on a slower neighbour.
+    // Other tiles (several batches, or large output) are placed at once.
     __device__ void run() {
         uint32_t* misc = MISC();
         uint64_t* off = OFF();
         const uint32_t tid = threadIdx.x;
+        uint8_t* slot = A.slots + (uint64_t)blockIdx.x * kSlotBytes;
+        bool pend = false;
+        uint32_t pt = 0, pnl = 0, ptotal = 0;
+        uint64_t pk0 = 0;
         while (true) {
             const uint32_t t = claim_tile(A.ws, &misc[2]);
-            if (t >= A.ntiles) break;
-            const uint64_t k0 = (uint64_t)t * kCL;
-            const uint32_t nl = (uint32_t)min((uint64_t)kCL, A.n - k0);
-            for (uint32_t j = tid; j <= nl; j += kWG) off[j] = A.in_off[k0 + j];
-            if (tid < kCL) COST()[tid] = 0;
-            __syncthreads();
-            const bool regular = __syncthreads_and(tid >= nl || frame_error(k0, tid) == 0) != 0;
-            // sweep 1: parse every batch, sizes into COST
+            const bool have = t < A.ntiles;
             LineState st;
-            uint32_t nb = 0, b0 = 0;
-            while (b0 < nl) {
-                b0 = batch(k0, nl, b0, regular, st);
-                nb++;
+            st.simple = true;
+            st.in = false;
+            st.bad = false;
+            uint32_t nb = 0, nl = 0, total = 0, e = 0, mylen = 0;
+            uint64_t k0 = 0;
+            bool regular = true;
+            if (have) {
+                k0 = (uint64_t)t * kCL;
+                nl = (uint32_t)min((uint64_t)kCL, A.n - k0);
+                for (uint32_t j = tid; j <= nl; j += kWG) off[j] = A.in_off[k0 + j];
+                if (tid < kCL) COST()[tid] = 0;
+                __syncthreads();
+                regular = __syncthreads_and(tid >= nl || frame_error(k0, tid) == 0) != 0;
+                // sweep 1: parse every batch, sizes into COST
+                uint32_t b0 = 0;
+                while (b0 < nl) {
+                    b0 = batch(k0, nl, b0, regular, st);
+                    nb++;
+                }
+                mylen = tid < nl ? COST()[tid] + 1 : 0u;
+                e = block_excl_scan(mylen, misc + 4, &total);
+                if (tid < nl) EOFF()[tid] = e;
+                if (tid == 0) publish_aggregate(A.status, t, total);
             }
-            // offsets inside the tile, then across tiles
-            uint32_t total;
-            const uint32_t mylen = tid < nl ? COST()[tid] + 1 : 0u;
-            const uint32_t e = block_excl_scan(mylen, misc + 4, &total);
-            if (tid < nl) EOFF()[tid] = e;
-            if (tid < 64) {
-                const uint64_t ex = lookback(A.status, t, total);
-                if (tid == 0) ((uint64_t*)misc)[6] = ex;
+            uint8_t* stage = st.simple ? PRE() : RAW();  // the buffer not holding this tile's tokens
+            // place the pending tile
+            if (pend) {
+                if (tid < 64) {
+                    const uint64_t ex = lookback_walk(A.status, pt, ptotal);
+                    if (tid == 0) ((uint64_t*)misc)[6] = ex;
+                }
+                __syncthreads();
+                const uint64_t pbase = ((uint64_t*)misc)[6];
+                if (tid < pnl) A.out_off[pk0 + tid + 1] += pbase;
+                if (A.out) {
+                    if (pbase + ptotal <= A.out_cap) copy_slot(slot, ptotal, pbase, stage);
+                    else if (tid == 0) atomicOr(&A.ws->enospc, 1u);
+                }
+                pend = false;
+                __syncthreads();
             }
-            __syncthreads();
-            const uint64_t gbase = ((uint64_t*)misc)[6];
-            if (tid < nl) A.out_off[k0 + tid + 1] = gbase + e + mylen;
+            if (!have) break;
             if (t == 0 && tid == 0) A.out_off[0] = 0;
-            const bool fits = gbase + total <= A.out_cap;
-            if (A.out && !fits && tid == 0) atomicOr(&A.ws->enospc, 1u);
-            if (A.out && fits) {
-                if (nb == 1) {
-                    emit(0, nl, st, gbase);
-                } else {
-                    b0 = 0;
-                    while (b0 < nl) {
-                        const uint32_t b1 = batch(k0, nl, b0, regular, st);
-                        emit(b0, b1, st, gbase);
-                        b0 = b1;
+            const bool defer = nb == 1 && total + 16 <= (uint32_t)kSlotBytes;
+            if (defer) {
+                if (tid < nl) A.out_off[k0 + tid + 1] = e + mylen;  // tile-relative for now
+                if (A.out) {
+                    emit(0, nl, st, 0, true);
+                    for (uint32_t c = tid; c < (total + 15) / 16; c += kWG)
+                        ((uint4*)slot)[c] = ((const uint4*)stage)[c];
+                }
+                pend = true;
+                pt = t;
+                pk0 = k0;
+                pnl = nl;
+                ptotal = total;
+            } else {
+                if (tid < 64) {
+                    const uint64_t ex = lookback_walk(A.status, t, total);
+                    if (tid == 0) ((uint64_t*)misc)[6] = ex;
+                }
+                __syncthreads();
+                const uint64_t gbase = ((uint64_t*)misc)[6];
+                if (tid < nl) A.out_off[k0 + tid + 1] = gbase + e + mylen;
+                const bool fits = gbase + total <= A.out_cap;
+                if (A.out && !fits && tid == 0) atomicOr(&A.ws->enospc, 1u);
+                if (A.out && fits) {
+                    if (nb == 1) {
+                        emit(0, nl, st, gbase);
+                    } else {
+                        uint32_t b0 = 0;
+                        while (b0 < nl) {
+                            const uint32_t b1 = batch(k0, nl, b0, regular, st);
+                            emit(b0, b1, st, gbase);
+                            b0 = b1;
+                        }
                     }
                 }
             }
@@ -1339,7 +1464,7 @@ size_t ws_bytes_for(int op, uint64_t n) {
             uint32_t nt = tiles_for(n, kCL);
             size_t st = ((size_t)nt * 8 + 255) & ~(size_t)255;
             size_t grid = (size_t)cus * kCompressWgPerCu;
-            return h + st + grid * kWG * kGenLane;
+            return h + st + grid * kWG * kGenLane + grid * kSlotBytes;
         }
         case ZS_OP_DECOMPRESS:
         case ZS_OP_DECOMPRESS_LINES:
@@ -1462,6 +1587,7 @@ zs_status zs_compress(const zs_dict* d, const uint8_t* in, uint64_t in_bytes, co
     uint64_t* status = (uint64_t*)(h + 1);
     size_t st_bytes = ((size_t)ntiles * 8 + 255) & ~(size_t)255;
     uint8_t* gen = (uint8_t*)status + st_bytes;
+    uint8_t* slots = gen + (size_t)di.cus * kCompressWgPerCu * kWG * kGenLane;
     if (launch_init(h, status, ntiles, (ResultOut*)res, s) != ZS_OK) return ZS_EDEVICE;
     CompressArgs a;
     a.tables = d->d_tables;
@@ -1478,6 +1604,7 @@ zs_status zs_compress(const zs_dict* d, const uint8_t* in, uint64_t in_bytes, co
     a.ws = h;
     a.status = status;
     a.gen = gen;
+    a.slots = slots;
     a.res = (ResultOut*)res;
     CompressLds cl = compress_lds(d->comp_bytes);
     int occ = 0;
