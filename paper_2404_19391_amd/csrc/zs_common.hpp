@@ -94,13 +94,19 @@ __device__ inline uint64_t lookback(uint64_t* status, uint32_t t, uint64_t agg) 
 }
 
 // ---- scans over one workgroup of kWG threads (wave64)
+// Inclusive scan over the 64 lanes (all lanes active): DPP row shifts inside
+// each row of 16 lanes, then the totals of the rows before, read from lanes
+// 15, 31 and 47.
 __device__ inline uint32_t wave_incl_scan(uint32_t v) {
-    const int lane = threadIdx.x & 63;
-#pragma unroll
-    for (int d = 1; d < 64; d <<= 1) {
-        uint32_t u = __shfl_up(v, d, 64);
-        if (lane >= d) v += u;
-    }
+    v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x111, 0xf, 0xf, true);  // row_shr:1
+    v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x112, 0xf, 0xf, true);  // row_shr:2
+    v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x114, 0xf, 0xf, true);  // row_shr:4
+    v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x118, 0xf, 0xf, true);  // row_shr:8
+    const uint32_t t0 = (uint32_t)__builtin_amdgcn_readlane((int)v, 15);
+    const uint32_t t1 = (uint32_t)__builtin_amdgcn_readlane((int)v, 31);
+    const uint32_t t2 = (uint32_t)__builtin_amdgcn_readlane((int)v, 47);
+    const uint32_t row = (threadIdx.x & 63) >> 4;
+    v += (row >= 1 ? t0 : 0u) + (row >= 2 ? t1 : 0u) + (row >= 3 ? t2 : 0u);
     return v;
 }
 
@@ -237,6 +243,27 @@ __device__ inline void load_range(const uint8_t* src, uint64_t limit, uint64_t l
             }
         }
     }
+}
+
+// Copy a deferred tile's bytes from its global slot to out[base, base+total),
+// through an LDS stage shifted to the destination's 16-byte alignment.  The
+// stage must hold total + 15 bytes.
+__device__ inline void copy_slot_out(uint8_t* out, const uint8_t* slot, uint32_t total, uint64_t base,
+                                     uint8_t* stage) {
+    const uintptr_t dst = (uintptr_t)(out + base);
+    const uint32_t shift = (uint32_t)(dst & 15);
+    const uint32_t nch = (total + 15) / 16;
+    for (uint32_t c = threadIdx.x; c < nch; c += kWG) {
+        const uint4 v = *(const uint4*)(slot + 16 * c);
+        const uint32_t w[4] = {v.x, v.y, v.z, v.w};
+#pragma unroll
+        for (int k = 0; k < 16; k++) {
+            if (16 * c + k < total) stage[shift + 16 * c + k] = (uint8_t)(w[k >> 2] >> (8 * (k & 3)));
+        }
+    }
+    __syncthreads();
+    flush_stage(out, base, base + total, dst - shift, stage);
+    __syncthreads();
 }
 
 }  // namespace zs

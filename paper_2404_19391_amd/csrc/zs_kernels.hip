@@ -16,7 +16,10 @@
 //            16-byte stores.
 // Decompression (Sec. IV-D-2) is byte-parallel: whole lines in LDS, escape
 // parity from a scan of space runs, expansion lengths from the LEN table, a
-// block scan for positions, expansions written to an LDS stage.
+// block scan for every byte's output position; then each thread builds 16
+// bytes of the destination from those positions and stores them at once.
+// Large jobs size every tile first, scan the tile totals and then emit at
+// known offsets, so that no workgroup waits for another.
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 #include <string.h>
@@ -160,7 +163,7 @@ __device__ inline bool ring_general(uint8_t* raw, uint32_t R, uint32_t len, uint
 
 template <int LK>
 struct Compressor {
-    const CompressArgs& A;
+    const CompressArgs A;
     uint8_t* smem;
     CompressLds L;
     const TableHeader* H;
@@ -183,18 +186,18 @@ struct Compressor {
         C = H->ncols;
     }
 
-    __device__ uint64_t* OFF() { return (uint64_t*)(smem + L.off); }
-    __device__ uint32_t* COST() { return (uint32_t*)(smem + L.cost); }
-    __device__ uint32_t* EOFF() { return (uint32_t*)(smem + L.eoff); }
-    __device__ uint16_t* LENS() { return (uint16_t*)(smem + L.lens); }
-    __device__ uint16_t* PERM() { return (uint16_t*)(smem + L.perm); }
-    __device__ uint32_t* MISC() { return (uint32_t*)(smem + L.misc); }
-    __device__ uint8_t* RAW() { return smem + L.raw; }
-    __device__ uint8_t* PRE() { return smem + L.pre; }
-    __device__ uint32_t* ESC() { return (uint32_t*)(smem + L.esc); }
+    __device__ __forceinline__ uint64_t* OFF() { return (uint64_t*)(smem + L.off); }
+    __device__ __forceinline__ uint32_t* COST() { return (uint32_t*)(smem + L.cost); }
+    __device__ __forceinline__ uint32_t* EOFF() { return (uint32_t*)(smem + L.eoff); }
+    __device__ __forceinline__ uint16_t* LENS() { return (uint16_t*)(smem + L.lens); }
+    __device__ __forceinline__ uint16_t* PERM() { return (uint16_t*)(smem + L.perm); }
+    __device__ __forceinline__ uint32_t* MISC() { return (uint32_t*)(smem + L.misc); }
+    __device__ __forceinline__ uint8_t* RAW() { return smem + L.raw; }
+    __device__ __forceinline__ uint8_t* PRE() { return smem + L.pre; }
+    __device__ __forceinline__ uint32_t* ESC() { return (uint32_t*)(smem + L.esc); }
 
     // Framing of line j of the tile (OFF staged).  0 = ok, else error kind.
-    __device__ uint32_t frame_error(uint64_t k0, uint32_t j) {
+    __device__ __forceinline__ uint32_t frame_error(uint64_t k0, uint32_t j) {
         const uint64_t a = OFF()[j], b = OFF()[j + 1];
         if (b <= a || b > A.in_bytes + 1) return kErrInval;
         if (b - a - 1 > ZS_MAX_LINE) return kErrInval;
@@ -210,7 +213,7 @@ struct Compressor {
         const uint32_t x = w ^ pat;
         return ~(((x & 0x7F7F7F7Fu) + 0x7F7F7F7Fu) | x) & 0x80808080u;
     }
-    __device__ void scan_labels(const uint8_t* raw, uint32_t R, uint32_t len, uint16_t* list, uint32_t cap,
+    __device__ __forceinline__ void scan_labels(const uint8_t* raw, uint32_t R, uint32_t len, uint16_t* list, uint32_t cap,
                                 uint32_t* nlab_out, bool* corrupt_out, bool* malformed_out, bool* over_out,
                                 bool* has_pct) {
         uint32_t inbr = 0;      // bracket state before the current word (0 or 0x80808080-style all-ones flag)
@@ -224,9 +227,10 @@ struct Compressor {
         for (uint32_t w = w0; w < end; w += 4) {
             const uint32_t next = *(const uint32_t*)(raw + w + 4);
             // flag bits of the bytes of this word that belong to the line
-            const uint32_t lo = R > w ? R - w : 0u, hi = end - w < 4u ? end - w : 4u;
+            // (clamps in signed arithmetic: see the note at the decoder's valid mask)
+            const uint32_t lo = (uint32_t)max((int32_t)R - (int32_t)w, 0), hi = min(end - w, 4u);
             const uint32_t inl = (0x80808080u << (8 * lo)) & (0x80808080u >> (8 * (4 - hi)));
-            const uint32_t nhi = end > w + 4 ? min(end - w - 4, 4u) : 0u;
+            const uint32_t nhi = (uint32_t)min(max((int32_t)end - (int32_t)w - 4, 0), 4);
             const uint32_t inl_n = nhi ? (0x80808080u >> (8 * (4 - nhi))) : 0u;
             // byte classes (valid only for bytes < 0x80; other bytes are corrupt anyway)
             const uint32_t ge30 = ((word & 0x7F7F7F7Fu) + 0x50505050u) & 0x80808080u;
@@ -281,7 +285,7 @@ struct Compressor {
     // its set (Sec. IV-A).  Markers are written over the raw line.  Sets
     // *overflow when a slot collides or an ID reaches 32; returns false when
     // rings stay open.
-    __device__ bool ring_fast(uint8_t* raw, uint32_t R, const uint16_t* list, uint32_t nlab, uint32_t maxlab,
+    __device__ __forceinline__ bool ring_fast(uint8_t* raw, uint32_t R, const uint16_t* list, uint32_t nlab, uint32_t maxlab,
                               int* delta, bool* overflow, bool* marked) {
         bool mk_any = false;
         uint32_t os[kSlots], mk[kSlots];
@@ -398,7 +402,7 @@ struct Compressor {
     // Process lines [b0, ...) of the tile as one batch: load, ring IDs, expand,
     // parse.  Fills COST for the batch lines and returns b1.  The per-lane
     // state needed for emission is left in `st`.
-    __device__ uint32_t batch(uint64_t k0, uint32_t nl, uint32_t b0, bool regular, LineState& st) {
+    __device__ __forceinline__ uint32_t batch(uint64_t k0, uint32_t nl, uint32_t b0, bool regular, LineState& st) {
         uint32_t* misc = MISC();
         uint64_t* off = OFF();
         uint16_t* lens = LENS();
@@ -603,7 +607,7 @@ struct Compressor {
     // at a time.  gbase: global output offset of the tile.
     // rel: write the batch at tile-relative offsets from stage byte 0 and leave it
     // there (one window; the caller copies it out later).
-    __device__ void emit(uint32_t b0, uint32_t b1, const LineState& st, uint64_t gbase, bool rel = false) {
+    __device__ __forceinline__ void emit(uint32_t b0, uint32_t b1, const LineState& st, uint64_t gbase, bool rel = false) {
         uint8_t* stage = st.simple ? PRE() : RAW();        // the buffer not holding tokens
         const uint8_t* pre = st.simple ? RAW() : PRE();
         const uint32_t* esc = ESC();
@@ -656,31 +660,12 @@ struct Compressor {
         }
     }
 
-    // Copy a deferred tile's bytes from its global slot to out[base, base+total),
-    // through an LDS stage shifted to the destination's 16-byte alignment.
-    __device__ void copy_slot(const uint8_t* slot, uint32_t total, uint64_t base, uint8_t* stage) {
-        const uintptr_t dst = (uintptr_t)(A.out + base);
-        const uint32_t shift = (uint32_t)(dst & 15);
-        const uint32_t nch = (total + 15) / 16;
-        for (uint32_t c = threadIdx.x; c < nch; c += kWG) {
-            const uint4 v = *(const uint4*)(slot + 16 * c);
-            const uint32_t w[4] = {v.x, v.y, v.z, v.w};
-#pragma unroll
-            for (int k = 0; k < 16; k++) {
-                if (16 * c + k < total) stage[shift + 16 * c + k] = (uint8_t)(w[k >> 2] >> (8 * (k & 3)));
-            }
-        }
-        __syncthreads();
-        flush_stage(A.out, base, base + total, dst - shift, stage);
-        __syncthreads();
-    }
-
     // Tiles are processed in ticket order.  A tile whose output fits one stage
     // window publishes its size as soon as it is parsed, parks its bytes in this
     // workgroup's global slot and is placed one tile later, when its
     // predecessors have published: no workgroup waits on a slower neighbour.
     // Other tiles (several batches, or large output) are placed at once.
-    __device__ void run() {
+    __device__ __forceinline__ void run() {
         uint32_t* misc = MISC();
         uint64_t* off = OFF();
         const uint32_t tid = threadIdx.x;
@@ -727,7 +712,7 @@ struct Compressor {
                 const uint64_t pbase = ((uint64_t*)misc)[6];
                 if (tid < pnl) A.out_off[pk0 + tid + 1] += pbase;
                 if (A.out) {
-                    if (pbase + ptotal <= A.out_cap) copy_slot(slot, ptotal, pbase, stage);
+                    if (pbase + ptotal <= A.out_cap) copy_slot_out(A.out, slot, ptotal, pbase, stage);
                     else if (tid == 0) atomicOr(&A.ws->enospc, 1u);
                 }
                 pend = false;
@@ -795,14 +780,19 @@ __global__ void __launch_bounds__(kWG) compress_kernel(CompressArgs a) {
 // Decompression (bulk and random access)
 // ============================================================================
 
-constexpr int kDL = 256;            // lines (or requests) per tile
-constexpr int kCbCap = 8192 + 16;   // LDS bytes of compressed lines per batch
-constexpr int kDStage = 24576;      // LDS output stage
-constexpr uint32_t kMaxCLine = 8191;  // longest compressed line accepted (newline excluded)
-constexpr int kSeg = kWG * 16;      // bytes per decode segment
+constexpr int kDL = 256;                 // lines (or requests) per tile
+constexpr int kCbCap = 8192 + 16;        // LDS bytes of compressed lines per batch
+constexpr uint32_t kMaxCLine = 8191;     // longest compressed line accepted (newline excluded)
+constexpr int kSeg = kWG * 16;           // bytes per decode segment
+constexpr int kDStage = 24576;           // LDS output stage (a multiple of 16)
+
+// Phases of a decompression call.  Large jobs run sizes -> scan of the tile
+// totals -> emit, with no workgroup ever waiting for another; small jobs (few
+// tiles) run one launch that places its tiles with a decoupled look-back.
+constexpr int kPhaseSizes = 0, kPhaseEmit = 1, kPhaseLookback = 2;
 
 struct DecompressLds {
-    uint32_t tabs, cb, stage, qoff, llen, lstart, bad, off, misc, total;
+    uint32_t tabs, cb, qoff, llen, bad, off, misc, stage, total, total_sizes;
 };
 
 __host__ __device__ inline DecompressLds decompress_lds() {
@@ -810,16 +800,16 @@ __host__ __device__ inline DecompressLds decompress_lds() {
     uint32_t o = 0;
     L.tabs = o;   o += 64 + 256 + 256 * kExpStride;  // header, LEN, EXP
     o = align16(o);
-    L.cb = o;     o += align16(kCbCap);
-    L.stage = o;  o += kDStage;
+    L.cb = o;     o += align16(kCbCap + 16);
     L.qoff = o;   o += (kDL + 1) * 4;
     L.llen = o;   o += kDL * 4;
-    L.lstart = o; o += kDL * 4;
     L.bad = o;    o += kDL;
     o = align16(o);
-    L.off = o;    o += (kDL + 1) * 16;  // a and b per line (gather) or offsets (bulk)
+    L.off = o;    o += (kDL + 1) * 16;  // a and b per line
     L.misc = o;   o += 256;
-    L.total = align16(o);
+    L.total_sizes = align16(o);         // the sizes phase needs nothing beyond this point
+    L.stage = L.total_sizes;
+    L.total = L.stage + kDStage;
     return L;
 }
 
@@ -835,16 +825,20 @@ struct DecompressArgs {
     uint64_t out_cap;
     uint64_t* out_off;
     uint32_t ntiles;
+    uint32_t tl;                // lines (requests) per tile, at most kDL
+    int phase;
     WsHeader* ws;
-    uint64_t* status;
+    uint64_t* status;           // look-back words (kPhaseLookback)
+    uint32_t* tile_total;       // output bytes per tile (written by kPhaseSizes)
+    const uint64_t* tile_base;  // exclusive prefix of tile_total, ntiles + 1 entries (read by kPhaseEmit)
     ResultOut* res;
 };
 
 // misc words of the decoder (uint32 indices)
-constexpr int kDmB1 = 0, kDmSlot = 2, kDmCarry = 4, kDmRun = 8, kDmScanA = 16, kDmScanB = 24, kDmBase64 = 20;
+constexpr int kDmB1 = 0, kDmSlot = 2, kDmScanA = 16, kDmScanB = 24, kDmBase64 = 32;
 
 struct Decoder {
-    const DecompressArgs& A;
+    const DecompressArgs A;
     uint64_t r0 = 0;  // first request of the current tile
     uint8_t* smem;
     DecompressLds L;
@@ -856,339 +850,425 @@ struct Decoder {
         LEN = smem + 64;
         EXP = smem + 64 + 256;
     }
-    __device__ uint32_t* QOFF() { return (uint32_t*)(smem + L.qoff); }
-    __device__ uint32_t* LLEN() { return (uint32_t*)(smem + L.llen); }
-    __device__ uint32_t* LSTART() { return (uint32_t*)(smem + L.lstart); }
-    __device__ uint8_t* BAD() { return smem + L.bad; }
-    __device__ uint64_t* LA() { return (uint64_t*)(smem + L.off); }  // [kDL+1] line start (abs)
-    __device__ uint64_t* LB() { return (uint64_t*)(smem + L.off) + (kDL + 1); }
-    __device__ uint32_t* MISC() { return (uint32_t*)(smem + L.misc); }
+    __device__ __forceinline__ uint8_t* CB() { return smem + L.cb; }
+    __device__ __forceinline__ uint32_t* QOFF() { return (uint32_t*)(smem + L.qoff); }
+    __device__ __forceinline__ uint32_t* LLEN() { return (uint32_t*)(smem + L.llen); }
+    __device__ __forceinline__ uint8_t* BAD() { return smem + L.bad; }
+    __device__ __forceinline__ uint64_t* LA() { return (uint64_t*)(smem + L.off); }  // [kDL+1] line start (abs)
+    __device__ __forceinline__ uint64_t* LB() { return (uint64_t*)(smem + L.off) + (kDL + 1); }
+    __device__ __forceinline__ uint32_t* MISC() { return (uint32_t*)(smem + L.misc); }
+    __device__ __forceinline__ uint8_t* STAGE() { return smem + L.stage; }
 
-    // Scan state for escape parity: number of trailing spaces and whether the
-    // whole piece is spaces.
-    struct Run {
-        uint32_t run;
-        uint32_t all;
-    };
-
-    // Exclusive scan of Run over the workgroup (segment carry folded in by the caller).
-    __device__ Run run_scan(Run v, Run* sc) {
-        const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-        Run inc = v;
+    // Stage writer of one thread: appends its bytes in order from stage index
+    // s0; whole dwords that hold only this thread's bytes are written as
+    // dwords, the partial ones at the two ends byte by byte (the neighbours
+    // write the rest of them).
+    struct Writer {
+        uint8_t* stage;
+        uint32_t s0, s, a;
+        uint64_t acc;  // bytes [a, s) not yet written, s - a < 4 between calls
+        __device__ __forceinline__ void put_dword(uint32_t at, uint32_t v) {
+            if (at >= s0) {
+                *(uint32_t*)(stage + at) = v;
+            } else {
 #pragma unroll
-        for (int d = 1; d < 64; d <<= 1) {
-            uint32_t ur = __shfl_up(inc.run, d, 64);
-            uint32_t ua = __shfl_up(inc.all, d, 64);
-            if (lane >= d && inc.all) {
-                inc.run += ur;
-                inc.all = ua;
+                for (int j = 0; j < 4; j++)
+                    if (at + j >= s0) stage[at + j] = (uint8_t)(v >> (8 * j));
             }
         }
-        if (lane == 63) sc[w] = inc;
-        __syncthreads();
-        Run pre = {0, 1};
-        for (int k = 0; k < w; k++) {
-            Run s = sc[k];
-            if (s.all) pre.run += s.run;
-            else pre = s;
+        // m (1..4) bytes: the low bytes of v, the others zero
+        __device__ __forceinline__ void add(uint32_t v, uint32_t m) {
+            acc |= (uint64_t)v << (8 * (s - a));
+            s += m;
+            if (s - a >= 4) {
+                put_dword(a, (uint32_t)acc);
+                acc >>= 32;
+                a += 4;
+            }
         }
-        __syncthreads();
-        // exclusive = combine(pre, inclusive-of-previous-lane)
-        uint32_t pr = __shfl_up(inc.run, 1, 64), pa = __shfl_up(inc.all, 1, 64);
-        Run ex;
-        if (lane == 0) {
-            ex = pre;
-        } else {
-            ex.run = pa ? pre.run + pr : pr;
-            ex.all = pa ? pre.all : 0;
+        __device__ __forceinline__ void finish() {
+            for (uint32_t x = a; x < s; x++)
+                if (x >= s0) stage[x] = (uint8_t)(acc >> (8 * (x - a)));
         }
-        return ex;
-    }
+    };
 
-    // One pass over the batch bytes [cb_lo, cb_hi) of lines [b0, b1).
-    // mode 0: sizes -> LLEN (raw, before bad-line adjustment) and BAD.
-    // mode 1: emit the bytes whose batch-relative output position lies in
-    //         [wlo, whi) into stage[sbase + pos].
-    __device__ void pass(uint32_t b0, uint32_t b1, uint32_t cb_lo, uint32_t cb_hi, int mode, uint64_t wlo,
-                         uint64_t whi, uint8_t* stage, intptr_t sbase, uint64_t gidx0) {
+    // One pass over the bytes [cb_lo, cb_hi) of lines [b0, b1) (Sec. IV-C: a
+    // byte is a literal iff an odd run of spaces precedes it; a code expands to
+    // its dictionary string).  Every line ends with its newline in CB.  Gives
+    // each byte its output length and records line ends (batch-relative) in
+    // LLEN.  With emit, the output bytes go to STAGE at index sbase + position;
+    // bytes whose index falls outside [0, kDStage) are left out and set *spill.
+    // Lines marked in BAD produce only their newline when mask_bad is set.
+    // Bytes that make a line corrupt mark it in BAD and set *err.  Returns the
+    // output bytes of the batch.
+    __device__ __forceinline__ uint32_t pass(uint32_t b0, uint32_t b1, uint32_t cb_lo, uint32_t cb_hi, bool mask_bad,
+                                             bool emit, int32_t sbase, bool* err, bool* spill) {
         const uint32_t tid = threadIdx.x;
-        const uint8_t* cb = smem + L.cb;
+        const uint8_t* cb = CB();
         const uint32_t* qoff = QOFF();
         uint8_t* bad = BAD();
-        uint32_t* misc = MISC();
-        Run* rsc = (Run*)(misc + kDmRun);
-        uint32_t* psc = misc + kDmScanA;
-        uint32_t carry_run = 0;
-        uint64_t carry_pos = 0;
+        uint32_t* llen = LLEN();
+        uint8_t* stage = STAGE();
+        uint32_t* psc = MISC() + kDmScanA;
+        uint32_t carry_pos = 0;
+        bool err_any = false, spill_any = false;
         const uint32_t c0 = cb_lo & ~15u;
         for (uint32_t seg = c0; seg < cb_hi; seg += kSeg) {
             const uint32_t x0 = seg + tid * 16;
             uint4 w4 = make_uint4(0, 0, 0, 0);
             if (x0 < cb_hi) w4 = *(const uint4*)(cb + x0);
-            // the 16 bytes as a 128-bit value, consumed from the low end
-            const uint64_t blo = (uint64_t)w4.x | ((uint64_t)w4.y << 32);
-            const uint64_t bhi = (uint64_t)w4.z | ((uint64_t)w4.w << 32);
-            const uint32_t lo = min(max(x0, cb_lo), x0 + 16), hi = max(min(x0 + 16, cb_hi), lo);
-            // run info of the piece [lo, hi)
-            Run me = {0, 1};
+            const uint32_t wv[4] = {w4.x, w4.y, w4.z, w4.w};
+#define ZS_BYTE(k) ((wv[(k) >> 2] >> (8 * ((k) & 3))) & 0xFFu)
+            // bytes of the chunk inside [cb_lo, cb_hi).  The clamps are signed: the
+            // form  a < b ? b - a : 0  in unsigned arithmetic was turned into an
+            // unconditional no-wrap subtraction, from which the optimizer
+            // concluded a <= b on every lane.
+            uint32_t valid = 0;
             {
-                uint64_t a = blo, b = bhi;
-                for (uint32_t x = x0; x < hi; x++) {
-                    const uint32_t c = (uint32_t)(a & 0xFF);
-                    a = (a >> 8) | (b << 56);
-                    b >>= 8;
-                    if (x >= lo) {
-                        if (c == ' ') me.run++;
-                        else { me.run = 0; me.all = 0; }
-                    }
+                const uint32_t lo = (uint32_t)min(max((int32_t)cb_lo - (int32_t)x0, 0), 16);
+                const uint32_t hi = (uint32_t)min(max((int32_t)cb_hi - (int32_t)x0, 0), 16);
+                if (hi > lo) valid = ((1u << hi) - 1u) & ~((1u << lo) - 1u);
+            }
+            uint32_t sp = 0;
+            uint32_t lp[4] = {0, 0, 0, 0};
+#pragma unroll
+            for (int k = 0; k < 16; k++) {
+                lp[k >> 2] |= (uint32_t)LEN[ZS_BYTE(k)] << (8 * (k & 3));
+                sp |= (ZS_BYTE(k) == ' ' ? 1u : 0u) << k;
+            }
+            sp &= valid;
+            // the run of spaces just before x0, read back from CB (lines end
+            // with a newline, so a run never reaches into the previous line)
+            uint32_t r = 0;
+            if (valid && x0 > cb_lo) {
+                for (uint32_t y = x0 - 16;; y -= 16) {
+                    const uint4 p4 = *(const uint4*)(cb + y);
+                    const uint32_t pw[4] = {p4.x, p4.y, p4.z, p4.w};
+                    uint32_t ps = 0;
+#pragma unroll
+                    for (int k = 0; k < 16; k++)
+                        ps |= ((((pw[k >> 2] >> (8 * (k & 3))) & 0xFFu) == ' ' && y + k >= cb_lo) ? 1u : 0u) << k;
+                    const uint32_t tr = (uint32_t)__builtin_clz(~(ps << 16));
+                    r += tr;
+                    if (tr < 16 || y <= cb_lo) break;
                 }
             }
-            Run ex = run_scan(me, rsc);
-            const uint32_t run = ex.all ? carry_run + ex.run : ex.run;
-            // line of the first byte: last q with qoff[q] <= lo
-            uint32_t q = b0;
-            if (lo < hi) {
-                uint32_t l = b0, r = b1;  // qoff[l] <= lo < qoff[r]
-                while (r - l > 1) {
-                    uint32_t mid = (l + r) >> 1;
-                    if (qoff[mid] <= lo) l = mid;
-                    else r = mid;
+            // the line of the first valid byte
+            uint32_t q = b0, nb = 0;
+            if (valid) {
+                const uint32_t xs = x0 + (uint32_t)__builtin_ctz(valid);  // the first valid byte
+                uint32_t l = b0, h = b1;
+                while (h - l > 1) {
+                    const uint32_t mid = (l + h) >> 1;
+                    if (qoff[mid] <= xs) l = mid;
+                    else h = mid;
                 }
                 q = l;
+                nb = qoff[q + 1];
             }
-            const uint32_t nb0 = qoff[q + 1];
-            const bool bad0 = mode == 1 && bad[q];
-            // lengths
-            uint32_t sum = 0;
-            {
-                uint32_t rr = run, qq = q, nb = nb0;
-                bool lbad = bad0;
-                uint64_t a = blo, b = bhi;
-                for (uint32_t x = x0; x < hi; x++) {
-                    const uint32_t c = (uint32_t)(a & 0xFF);
-                    a = (a >> 8) | (b << 56);
-                    b >>= 8;
-                    if (x < lo) continue;
-                    if (x >= nb) {
-                        do {
-                            qq++;
-                            nb = qoff[qq + 1];
-                        } while (x >= nb);
-                        if (mode == 1) lbad = bad[qq];
-                    }
-                    const bool term = x + 1 == nb;
-                    const bool lit = rr & 1;
-                    uint32_t len;
-                    bool err = false;
-                    if (term) {
-                        len = 1;
-                        err = lit;  // dangling escape
-                    } else if (lit) {
-                        len = 1;
-                        err = c < 0x20 || c > 0x7E;
-                    } else if (c == ' ') {
-                        len = 0;
-                    } else {
-                        len = LEN[c];
-                        err = len == 0;
-                    }
-                    rr = (c == ' ' && !term) ? rr + 1 : 0;
-                    if (mode == 0) {
-                        if (err && !bad[qq]) bad[qq] = kErrCorrupt;
-                    } else if (lbad && !term) {
-                        len = 0;
-                    }
-                    sum += len;
+            const uint32_t qfirst = q;
+            bool qbad = mask_bad && valid && bad[q] != 0;
+            uint32_t sum = 0, term = 0, lit = 0;
+#pragma unroll
+            for (int k = 0; k < 16; k++) {
+                const uint32_t x = x0 + k;
+                const bool isv = (valid >> k) & 1;
+                if (isv && x >= nb) {
+                    do {
+                        q++;
+                        nb = qoff[q + 1];
+                    } while (x >= nb);
+                    qbad = mask_bad && bad[q] != 0;
                 }
+                const uint32_t ck = ZS_BYTE(k);
+                const uint32_t tl = (lp[k >> 2] >> (8 * (k & 3))) & 0xFFu;
+                const bool iss = (sp >> k) & 1;
+                const bool ist = isv && (x + 1 == nb);
+                const bool islit = isv && (r & 1);
+                uint32_t len;
+                bool e = false;
+                if (!isv) len = 0;
+                else if (qbad) len = ist ? 1u : 0u;
+                else if (ist) { len = 1; e = islit; }                         // a dangling escape
+                else if (islit) { len = 1; e = ck < 0x20u || ck > 0x7Eu; }    // literal outside 0x20..0x7E
+                else if (iss) len = 0;
+                else { len = tl; e = tl == 0; }                              // undefined code
+                if (e) {
+                    bad[q] = (uint8_t)kErrCorrupt;
+                    err_any = true;
+                }
+                term |= (ist ? 1u : 0u) << k;
+                lit |= (islit && !ist ? 1u : 0u) << k;
+                lp[k >> 2] = (lp[k >> 2] & ~(0xFFu << (8 * (k & 3)))) | (len << (8 * (k & 3)));
+                sum += len;
+                r = iss ? r + 1 : 0u;
             }
             uint32_t segtot;
-            const uint32_t pos32 = block_excl_scan(sum, psc, &segtot);
-            {
-                uint64_t pos = carry_pos + pos32;
-                uint32_t rr = run, qq = q, nb = nb0;
-                bool lbad = bad0;
-                uint64_t a = blo, b = bhi;
-                for (uint32_t x = x0; x < hi; x++) {
-                    const uint32_t c = (uint32_t)(a & 0xFF);
-                    a = (a >> 8) | (b << 56);
-                    b >>= 8;
-                    if (x < lo) continue;
-                    if (x >= nb) {
-                        do {
-                            qq++;
-                            nb = qoff[qq + 1];
-                        } while (x >= nb);
-                        if (mode == 1) lbad = bad[qq];
-                    }
-                    const bool term = x + 1 == nb;
-                    const bool lit = rr & 1;
-                    rr = (c == ' ' && !term) ? rr + 1 : 0;
-                    if (mode == 0) {
-                        const uint32_t len = (term || lit) ? 1u : (c == ' ' ? 0u : (uint32_t)LEN[c]);
-                        pos += len;
-                        if (term) LLEN()[qq] = (uint32_t)pos;  // end of line qq (batch-relative)
-                    } else if (!lbad || term) {
-                        if (term || lit) {
-                            if (pos >= wlo && pos < whi) stage[sbase + (intptr_t)pos] = term ? '\n' : (uint8_t)c;
-                            pos += 1;
-                        } else if (c != ' ') {
-                            const uint32_t len = LEN[c];
-                            const uint8_t* e = EXP + c * kExpStride;
-                            if (pos >= wlo && pos + len <= whi) {
-                                uint8_t* d = stage + sbase + (intptr_t)pos;
-                                for (uint32_t j = 0; j < len; j++) d[j] = e[j];
+            const uint32_t pos0 = carry_pos + block_excl_scan(sum, psc, &segtot);
+            if (term) {
+                uint32_t qq = qfirst, pos = pos0;
+#pragma unroll
+                for (int k = 0; k < 16; k++) {
+                    pos += (lp[k >> 2] >> (8 * (k & 3))) & 0xFFu;
+                    if ((term >> k) & 1) llen[qq++] = pos;
+                }
+            }
+            if (emit && sum) {
+                const int32_t st0 = sbase + (int32_t)pos0;
+                if (st0 >= 0 && st0 + (int32_t)sum <= kDStage) {
+                    Writer wr;
+                    wr.stage = stage;
+                    wr.s0 = wr.s = (uint32_t)st0;
+                    wr.a = wr.s0 & ~3u;
+                    wr.acc = 0;
+#pragma unroll
+                    for (int k = 0; k < 16; k++) {
+                        const uint32_t len = (lp[k >> 2] >> (8 * (k & 3))) & 0xFFu;
+                        if (len) {
+                            const uint32_t ck = ZS_BYTE(k);
+                            if (((term | lit) >> k) & 1) {
+                                wr.add(((term >> k) & 1) ? (uint32_t)'\n' : ck, 1);
                             } else {
-                                for (uint32_t j = 0; j < len; j++) {
-                                    const uint64_t p = pos + j;
-                                    if (p >= wlo && p < whi) stage[sbase + (intptr_t)p] = e[j];
+                                const uint2 e = *(const uint2*)(EXP + ck * kExpStride);
+                                wr.add(e.x, min(len, 4u));
+                                if (len > 4) wr.add(e.y, min(len - 4, 4u));
+                                if (len > 8) {
+                                    const uint2 f = *(const uint2*)(EXP + ck * kExpStride + 8);
+                                    wr.add(f.x, min(len - 8, 4u));
+                                    if (len > 12) wr.add(f.y, len - 12);
                                 }
                             }
-                            pos += len;
+                        }
+                    }
+                    wr.finish();
+                } else {
+                    // part of this thread's bytes lies outside the stage window
+                    spill_any = true;
+                    int32_t sx = st0;
+#pragma unroll 1
+                    for (int k = 0; k < 16; k++) {
+                        const uint32_t len = (lp[k >> 2] >> (8 * (k & 3))) & 0xFFu;
+                        const uint32_t ck = (wv[k >> 2] >> (8 * (k & 3))) & 0xFFu;
+                        for (uint32_t j = 0; j < len; j++, sx++) {
+                            if (sx < 0 || sx >= kDStage) continue;
+                            uint32_t b;
+                            if ((term >> k) & 1) b = '\n';
+                            else if ((lit >> k) & 1) b = ck;
+                            else b = EXP[ck * kExpStride + j];
+                            stage[sx] = (uint8_t)b;
                         }
                     }
                 }
             }
-            // carries for the next segment: the last thread's inclusive state
-            if (tid == kWG - 1) {
-                uint32_t rr = me.all ? (ex.all ? carry_run + ex.run : ex.run) + me.run : me.run;
-                misc[kDmCarry] = rr;
-            }
-            __syncthreads();
-            carry_run = misc[kDmCarry];
+#undef ZS_BYTE
             carry_pos += segtot;
-            __syncthreads();
         }
-        (void)gidx0;
+        *err = __syncthreads_or(err_any) != 0;
+        if (spill) *spill = __syncthreads_or(spill_any) != 0;
+        return carry_pos;
     }
 
-    __device__ void run() {
-        uint32_t* misc = MISC();
+    // Size a loaded batch: one pass, and a second one with the lines found
+    // corrupt masked.  Reports the corrupt lines.
+    __device__ __forceinline__ uint32_t size_batch(uint32_t b0, uint32_t b1, uint32_t cb_lo, uint32_t cb_hi,
+                                                   bool anybad) {
+        bool err;
+        uint32_t T = pass(b0, b1, cb_lo, cb_hi, anybad, false, 0, &err, nullptr);
+        if (err) {
+            T = pass(b0, b1, cb_lo, cb_hi, true, false, 0, &err, nullptr);
+            const uint32_t q = b0 + threadIdx.x;
+            if (q < b1 && BAD()[q] == kErrCorrupt) note_error(A.ws, r0 + q, kErrCorrupt);
+        }
+        __syncthreads();
+        return T;
+    }
+
+    // Decode a loaded batch into out[g0, ...): passes that write the stage,
+    // flushed with 16-byte stores on the destination's 16-byte grid; a batch
+    // whose output exceeds the stage goes out in several windows.  Returns the
+    // batch's output bytes; line ends are left in LLEN.
+    __device__ __forceinline__ uint32_t decode_batch(uint32_t b0, uint32_t b1, uint32_t cb_lo, uint32_t cb_hi,
+                                                     bool anybad, uint64_t g0, bool write) {
+        bool err, spill;
+        const uintptr_t dst = (uintptr_t)(A.out + g0);
+        const uintptr_t a0 = dst & ~(uintptr_t)15;
+        const int32_t lead = (int32_t)(dst - a0);
+        uint32_t T = pass(b0, b1, cb_lo, cb_hi, anybad, write, lead, &err, &spill);
+        if (err) {
+            T = pass(b0, b1, cb_lo, cb_hi, true, write, lead, &err, &spill);
+            const uint32_t q = b0 + threadIdx.x;
+            if (q < b1 && BAD()[q] == kErrCorrupt) note_error(A.ws, r0 + q, kErrCorrupt);
+        }
+        if (!write) {
+            __syncthreads();
+            return T;
+        }
+        uint8_t* stage = STAGE();
+        // window w holds destination bytes [a0 + w kDStage, a0 + (w + 1) kDStage)
+        for (uint32_t w = 0;; w++) {
+            const uint64_t wlo = (uint64_t)w * kDStage;  // relative to a0
+            if (w > 0) pass(b0, b1, cb_lo, cb_hi, true, true, lead - (int32_t)wlo, &err, &spill);
+            const int64_t wrel = (int64_t)wlo - lead;  // batch position of the window's first byte
+            uint64_t lo = (uint64_t)max(wrel, (int64_t)0), hi = (uint64_t)(wrel + kDStage);
+            if (hi > T) hi = T;
+            __syncthreads();
+            flush_stage(A.out, g0 + lo, g0 + hi, a0 + (uintptr_t)wlo, stage);
+            __syncthreads();
+            if (!spill || hi >= T) break;
+        }
+        return T;
+    }
+
+    // Framing of the requests of tile t; returns the number of lines and sets
+    // *regular (no framing error in the tile).
+    __device__ __forceinline__ uint32_t setup_tile(uint32_t t, bool* regular) {
         const uint32_t tid = threadIdx.x;
         const bool gather = A.ids != nullptr;
         uint8_t* bad = BAD();
-        uint32_t* qoff = QOFF();
-        uint32_t* llen = LLEN();
-        uint32_t* lstart = LSTART();
         uint64_t* la = LA();
         uint64_t* lb = LB();
-        uint8_t* cb = smem + L.cb;
+        r0 = (uint64_t)t * A.tl;
+        const uint32_t nl = (uint32_t)min((uint64_t)A.tl, A.nreq - r0);
+        if (tid < nl) {
+            const uint64_t r = r0 + tid;
+            uint32_t fe = 0;
+            const uint64_t id = gather ? A.ids[r] : r;
+            uint64_t a = 0, b = 0;
+            if (id >= A.n) {
+                fe = kErrInval;
+            } else {
+                a = A.in_off[id];
+                b = A.in_off[id + 1];
+                if (b <= a || b > A.in_bytes + 1 || b - a - 1 > kMaxCLine) fe = kErrInval;
+                else if (b == A.in_bytes + 1 && id + 1 != A.n) fe = kErrInval;
+            }
+            la[tid] = a;
+            lb[tid] = b;
+            bad[tid] = (uint8_t)fe;
+            if (fe) note_error(A.ws, r, fe);
+        }
+        *regular = __syncthreads_and(tid >= nl || bad[tid] == 0) != 0;
+        return nl;
+    }
+
+    // Output offsets of lines [b0, b1) whose batch starts at global offset g.
+    __device__ __forceinline__ void write_offsets(uint32_t b0, uint32_t b1, uint64_t g) {
+        const uint32_t q = b0 + threadIdx.x;
+        if (q < b1) A.out_off[r0 + q + 1] = g + LLEN()[q];
+    }
+
+    // Sizes and emission with the tile's base known (kPhaseSizes, kPhaseEmit).
+    // Tiles are taken in a fixed order; no workgroup waits for another.
+    __device__ __forceinline__ void run_static() {
+        const uint32_t tid = threadIdx.x;
+        const bool gather = A.ids != nullptr;
+        const bool emit_phase = A.phase == kPhaseEmit;
+        for (uint32_t t = blockIdx.x; t < A.ntiles; t += gridDim.x) {
+            bool regular;
+            const uint32_t nl = setup_tile(t, &regular);
+            uint64_t gbase = 0;
+            bool fits = false;
+            if (emit_phase) {
+                gbase = A.tile_base[t];
+                fits = A.tile_base[t + 1] <= A.out_cap;
+                if (!fits && tid == 0) atomicOr(&A.ws->enospc, 1u);
+                if (t == 0 && tid == 0) A.out_off[0] = 0;
+            }
+            uint32_t tpos = 0, b0 = 0;
+            while (b0 < nl) {
+                uint32_t b1, cb_lo, cb_hi;
+                bool anybad;
+                load_batch(b0, nl, regular, gather, &b1, &cb_lo, &cb_hi, &anybad);
+                uint32_t T;
+                if (emit_phase) {
+                    T = decode_batch(b0, b1, cb_lo, cb_hi, anybad, gbase + tpos, A.out && fits);
+                    write_offsets(b0, b1, gbase + tpos);
+                } else {
+                    T = size_batch(b0, b1, cb_lo, cb_hi, anybad);
+                }
+                tpos += T;
+                b0 = b1;
+                __syncthreads();
+            }
+            if (!emit_phase && tid == 0) A.tile_total[t] = tpos;
+        }
+        if (emit_phase) finish_workgroup(A.ws, A.res, gridDim.x);
+    }
+
+    // One launch for a few tiles (kPhaseLookback): tiles in ticket order, each
+    // placed by a decoupled look-back once its size is known.
+    __device__ __forceinline__ void run_lookback() {
+        uint32_t* misc = MISC();
+        uint32_t* llen = LLEN();
+        const uint32_t tid = threadIdx.x;
+        const bool gather = A.ids != nullptr;
         while (true) {
             const uint32_t t = claim_tile(A.ws, &misc[kDmSlot]);
             if (t >= A.ntiles) break;
-            r0 = (uint64_t)t * kDL;
-            const uint32_t nl = (uint32_t)min((uint64_t)kDL, A.nreq - r0);
-            // ---- framing of every line of the tile
-            if (tid < nl) {
-                const uint64_t r = r0 + tid;
-                uint32_t fe = 0;
-                uint64_t id = gather ? A.ids[r] : r;
-                uint64_t a = 0, b = 0;
-                if (id >= A.n) {
-                    fe = kErrInval;
-                } else {
-                    a = A.in_off[id];
-                    b = A.in_off[id + 1];
-                    if (b <= a || b > A.in_bytes + 1 || b - a - 1 > kMaxCLine) fe = kErrInval;
-                    else if (b == A.in_bytes + 1 && id + 1 != A.n) fe = kErrInval;
-                }
-                la[tid] = a;
-                lb[tid] = b;
-                bad[tid] = (uint8_t)fe;
-                if (fe) note_error(A.ws, r, fe);
-                llen[tid] = 0;
-            }
-            __syncthreads();
-            const bool regular = __syncthreads_and(tid >= nl || bad[tid] == 0) != 0;
-            // ---- sweep 1: sizes
-            uint32_t nb = 0;
-            uint32_t b0 = 0;
-            uint32_t last_b1 = 0, last_lo = 0, last_hi = 0;
+            bool regular;
+            const uint32_t nl = setup_tile(t, &regular);
+            uint32_t tpos = 0, b0 = 0, nb = 0, T = 0, lo = 0, hi = 0, lb1 = 0;
+            bool lbad = false;
             while (b0 < nl) {
-                uint32_t b1, cb_lo, cb_hi;
-                load_batch(b0, nl, regular, gather, &b1, &cb_lo, &cb_hi);
-                pass(b0, b1, cb_lo, cb_hi, 0, 0, 0, nullptr, 0, 0);
+                uint32_t b1;
+                bool anybad;
+                load_batch(b0, nl, regular, gather, &b1, &lo, &hi, &anybad);
+                T = size_batch(b0, b1, lo, hi, anybad);
+                lb1 = b1;
+                lbad = anybad;
+                // line ends relative to the tile
+                const uint32_t q = b0 + tid;
+                if (q < b1) llen[q] += tpos;
                 __syncthreads();
-                // LLEN holds line ends; turn them into lengths (bad lines: just the newline)
-                {
-                    uint32_t q = b0 + tid;
-                    uint32_t v = 0;
-                    if (q < b1) {
-                        uint32_t end = llen[q];
-                        uint32_t prev = (q > b0) ? llen[q - 1] : 0u;
-                        v = bad[q] ? 1u : end - prev;
-                        if (bad[q] == kErrCorrupt) note_error(A.ws, r0 + q, kErrCorrupt);
-                    }
-                    __syncthreads();
-                    if (q < b1) llen[q] = v;
-                }
-                __syncthreads();
-                nb++;
-                last_b1 = b1;
-                last_lo = cb_lo;
-                last_hi = cb_hi;
+                tpos += T;
                 b0 = b1;
+                nb++;
             }
-            // ---- offsets
-            uint32_t total;
-            const uint32_t mylen = tid < nl ? llen[tid] : 0u;
-            const uint32_t e = block_excl_scan(mylen, misc + kDmScanB, &total);
-            if (tid < nl) lstart[tid] = e;
             if (tid < 64) {
-                uint64_t ex = lookback(A.status, t, total);
+                const uint64_t ex = lookback(A.status, t, tpos);
                 if (tid == 0) ((uint64_t*)misc)[kDmBase64 / 2] = ex;
             }
             __syncthreads();
             const uint64_t gbase = ((uint64_t*)misc)[kDmBase64 / 2];
-            if (tid < nl) A.out_off[r0 + tid + 1] = gbase + e + mylen;
             if (t == 0 && tid == 0) A.out_off[0] = 0;
-            const bool fits = gbase + total <= A.out_cap;
-            if (A.out && !fits && tid == 0) atomicOr(&A.ws->enospc, 1u);
+            write_offsets(0, nl, gbase);
+            const bool fits = gbase + tpos <= A.out_cap;
+            if (!fits && tid == 0) atomicOr(&A.ws->enospc, 1u);
             if (A.out && fits) {
-                b0 = 0;
-                while (b0 < nl) {
-                    uint32_t b1, cb_lo, cb_hi;
-                    if (nb == 1) {
-                        b1 = last_b1;
-                        cb_lo = last_lo;
-                        cb_hi = last_hi;
-                    } else {
-                        load_batch(b0, nl, regular, gather, &b1, &cb_lo, &cb_hi);
-                    }
-                    // batch output range, tile-relative
-                    const uint64_t o0 = lstart[b0];
-                    const uint64_t o1 = (uint64_t)lstart[b1 - 1] + llen[b1 - 1];
-                    uint64_t wlo = o0;
-                    while (wlo < o1) {
-                        uint64_t whi = min(o1, wlo + (uint64_t)(kDStage - 16));
-                        const uintptr_t a0 = ((uintptr_t)(A.out + gbase + wlo)) & ~(uintptr_t)15;
-                        // stage index of batch-relative position p: (out + gbase + o0 + p) - a0
-                        const intptr_t sbase = (intptr_t)((uintptr_t)(A.out + gbase + o0) - a0);
-                        pass(b0, b1, cb_lo, cb_hi, 1, wlo - o0, whi - o0, smem + L.stage, sbase, 0);
+                if (nb == 1) {
+                    __syncthreads();
+                    decode_batch(0, lb1, lo, hi, lbad, gbase, true);
+                } else {
+                    uint32_t g = 0;
+                    b0 = 0;
+                    while (b0 < nl) {
+                        uint32_t b1;
+                        bool anybad;
+                        load_batch(b0, nl, regular, gather, &b1, &lo, &hi, &anybad);
+                        g += decode_batch(b0, b1, lo, hi, anybad, gbase + g, true);
+                        b0 = b1;
                         __syncthreads();
-                        flush_stage(A.out, gbase + wlo, gbase + whi, a0, smem + L.stage);
-                        __syncthreads();
-                        wlo = whi;
                     }
-                    b0 = b1;
                 }
             }
             __syncthreads();
         }
         finish_workgroup(A.ws, A.res, gridDim.x);
-        (void)cb;
     }
 
     // Choose the batch [b0, b1) that fits the CB buffer and load it.  Lines are
-    // packed at qoff[q]; every line ends with its newline in CB.
-    __device__ void load_batch(uint32_t b0, uint32_t nl, bool regular, bool gather, uint32_t* b1_out,
-                               uint32_t* cb_lo, uint32_t* cb_hi) {
+    // packed at qoff[q]; every line ends with its newline in CB (a line whose
+    // last byte is not a newline is bad, and its last CB byte is made one so
+    // that escape runs never cross lines).
+    __device__ __forceinline__ void load_batch(uint32_t b0, uint32_t nl, bool regular, bool gather, uint32_t* b1_out,
+                                               uint32_t* cb_lo, uint32_t* cb_hi, bool* anybad) {
         const uint32_t tid = threadIdx.x;
         uint32_t* misc = MISC();
         uint8_t* bad = BAD();
         uint32_t* qoff = QOFF();
         uint64_t* la = LA();
         uint64_t* lb = LB();
-        uint8_t* cb = smem + L.cb;
+        uint8_t* cb = CB();
         // packed sizes: bad lines get a lone newline so that line framing stays intact
         const uint32_t q = b0 + tid;
         uint32_t sz = 0;
@@ -1219,6 +1299,7 @@ struct Decoder {
             load_range(A.in, A.in_bytes, lo, hi, a0, cb);
             __syncthreads();
             if (tid == 0 && lb[b1 - 1] == A.in_bytes + 1) cb[qoff[b1] - 1] = '\n';
+            __syncthreads();
         } else {
             // gather: each thread fills 16-byte chunks of CB; the line of a
             // chunk's first byte comes from a search of qoff, the 16 source
@@ -1259,13 +1340,16 @@ struct Decoder {
             __syncthreads();
         }
         // the newline must be where the index says
-        if (q < b1 && !bad[q]) {
-            if (cb[qoff[q + 1] - 1] != '\n') {
+        bool isbad = false;
+        if (q < b1) {
+            if (!bad[q] && cb[qoff[q + 1] - 1] != '\n') {
                 bad[q] = kErrInval;
                 note_error(A.ws, r0 + q, kErrInval);
+                cb[qoff[q + 1] - 1] = '\n';
             }
+            isbad = bad[q] != 0;
         }
-        __syncthreads();
+        *anybad = __syncthreads_or(isbad) != 0;
         *b1_out = b1;
         *cb_lo = qoff[b0];
         *cb_hi = qoff[b1];
@@ -1289,15 +1373,45 @@ __global__ void __launch_bounds__(kWG) decompress_kernel(DecompressArgs a) {
     }
     __syncthreads();
     Decoder d(a, smem);
-    d.run();
+    if (a.phase == kPhaseLookback) d.run_lookback();
+    else d.run_static();
+}
+
+// Exclusive prefix of n per-tile totals: base[i] = total[0] + ... + total[i-1],
+// base[n] = the sum.  One workgroup of 1024 threads, each scanning a run of
+// consecutive tiles.
+constexpr int kScanWG = 1024;
+__global__ void __launch_bounds__(kScanWG) tile_scan_kernel(const uint32_t* total, uint64_t* base, uint32_t n) {
+    __shared__ uint64_t wsum[kScanWG / 64];
+    const uint32_t tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+    const uint32_t per = (n + kScanWG - 1) / kScanWG;
+    const uint32_t i0 = min(n, tid * per), i1 = min(n, i0 + per);
+    uint64_t s = 0;
+    for (uint32_t i = i0; i < i1; i++) s += total[i];
+    const uint64_t inc = wave_incl_scan64(s);
+    if (lane == 63) wsum[w] = inc;
+    __syncthreads();
+    uint64_t before = 0, all = 0;
+#pragma unroll
+    for (int k = 0; k < kScanWG / 64; k++) {
+        const uint64_t v = wsum[k];
+        before += ((uint32_t)k < w) ? v : 0ull;
+        all += v;
+    }
+    uint64_t run = before + inc - s;
+    for (uint32_t i = i0; i < i1; i++) {
+        base[i] = run;
+        run += total[i];
+    }
+    if (tid == 0) base[n] = all;
 }
 
 // ============================================================================
 // Line index
 // ============================================================================
 
-constexpr int kIdxPer = 256;              // bytes per thread
-constexpr int kIdxTile = kWG * kIdxPer;    // bytes per tile
+constexpr int kIdxRounds = 8;                    // 16-byte loads per thread per tile
+constexpr int kIdxTile = kWG * 16 * kIdxRounds;  // bytes per tile (32 KiB)
 
 struct IndexArgs {
     const uint8_t* buf;
@@ -1307,7 +1421,8 @@ struct IndexArgs {
     uint64_t* n_lines_out;
     uint32_t ntiles;
     WsHeader* ws;
-    uint64_t* status;
+    uint32_t* tile_total;       // newlines per tile (count phase)
+    const uint64_t* tile_base;  // exclusive prefix of tile_total (write phase)
     ResultOut* res;
 };
 
@@ -1331,43 +1446,85 @@ __device__ inline uint4 load16_or_pad(const uint8_t* buf, uint64_t len, uint64_t
     return make_uint4(w[0], w[1], w[2], w[3]);
 }
 
-__global__ void __launch_bounds__(kWG) index_kernel(IndexArgs a) {
-    __shared__ uint64_t sc[8];
-    __shared__ uint32_t slot[4];
-    __shared__ uint64_t sbase;
-    const uint32_t tid = threadIdx.x;
+// Count phase: newlines per tile.  Round k of a tile covers bytes
+// [4096 k, 4096 k + 4096), 16 per thread, so every load is coalesced.
+__global__ void __launch_bounds__(kWG) index_count_kernel(IndexArgs a) {
+    __shared__ uint32_t sc[kWaves];
+    const uint32_t tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
     const bool aligned = (((uintptr_t)a.buf) & 15) == 0;
-    while (true) {
-        const uint32_t t = claim_tile(a.ws, &slot[0]);
-        if (t >= a.ntiles) break;
-        const uint64_t x0 = (uint64_t)t * kIdxTile + (uint64_t)tid * kIdxPer;
-        uint64_t cnt = 0;
-        for (int k = 0; k < kIdxPer / 16; k++) {
-            const uint4 v = load16_or_pad(a.buf, a.len, x0 + 16 * k, aligned);
+    for (uint32_t t = blockIdx.x; t < a.ntiles; t += gridDim.x) {
+        const uint64_t tb = (uint64_t)t * kIdxTile;
+        uint32_t cnt = 0;
+#pragma unroll
+        for (int k = 0; k < kIdxRounds; k++) {
+            const uint4 v = load16_or_pad(a.buf, a.len, tb + 4096u * k + 16u * tid, aligned);
             cnt += __popc(newline_bits(v.x)) + __popc(newline_bits(v.y)) + __popc(newline_bits(v.z)) +
                    __popc(newline_bits(v.w));
         }
-        uint64_t tot;
-        uint64_t ex = block_excl_scan64(cnt, sc, &tot);
-        if (tid < 64) {
-            uint64_t b = lookback(a.status, t, tot);
-            if (tid == 0) sbase = b;
+        const uint32_t s = (uint32_t)wave_sum64(cnt);
+        if (lane == 0) sc[w] = s;
+        __syncthreads();
+        if (tid == 0) {
+            uint32_t tot = 0;
+            for (int k = 0; k < kWaves; k++) tot += sc[k];
+            a.tile_total[t] = tot;
         }
         __syncthreads();
-        uint64_t k1 = sbase + ex;  // newlines before this thread's bytes
-        if (cnt) {
-            for (int k = 0; k < kIdxPer / 16; k++) {
-                const uint4 v = load16_or_pad(a.buf, a.len, x0 + 16 * k, aligned);
-                const uint32_t wv[4] = {newline_bits(v.x), newline_bits(v.y), newline_bits(v.z), newline_bits(v.w)};
+    }
+}
+
+// Write phase: the same loads, newline masks kept in registers, the eight
+// round counts scanned together, offsets written in order from the tile's
+// base.
+__global__ void __launch_bounds__(kWG) index_write_kernel(IndexArgs a) {
+    __shared__ uint32_t sc[kWaves][kIdxRounds];
+    const uint32_t tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+    const bool aligned = (((uintptr_t)a.buf) & 15) == 0;
+    for (uint32_t t = blockIdx.x; t < a.ntiles; t += gridDim.x) {
+        const uint64_t tb = (uint64_t)t * kIdxTile;
+        uint32_t mask[4 * kIdxRounds], cnt[kIdxRounds], ex[kIdxRounds];
 #pragma unroll
-                for (int w = 0; w < 4; w++) {
-                    uint32_t m = wv[w];
-                    while (m) {
-                        const int bit = __builtin_ctz(m);
-                        m &= m - 1;
-                        k1++;
-                        if (k1 < a.off_cap) a.off[k1] = x0 + 16 * k + 4 * w + (bit >> 3) + 1;
-                    }
+        for (int k = 0; k < kIdxRounds; k++) {
+            const uint4 v = load16_or_pad(a.buf, a.len, tb + 4096u * k + 16u * tid, aligned);
+            mask[4 * k + 0] = newline_bits(v.x);
+            mask[4 * k + 1] = newline_bits(v.y);
+            mask[4 * k + 2] = newline_bits(v.z);
+            mask[4 * k + 3] = newline_bits(v.w);
+            cnt[k] = __popc(mask[4 * k]) + __popc(mask[4 * k + 1]) + __popc(mask[4 * k + 2]) + __popc(mask[4 * k + 3]);
+        }
+#pragma unroll
+        for (int k = 0; k < kIdxRounds; k++) {
+            const uint32_t inc = wave_incl_scan(cnt[k]);
+            ex[k] = inc - cnt[k];
+            if (lane == 63) sc[w][k] = inc;
+        }
+        __syncthreads();
+        uint32_t tot = 0;
+#pragma unroll
+        for (int k = 0; k < kIdxRounds; k++) {
+            uint32_t before = 0, round = 0;
+#pragma unroll
+            for (int ww = 0; ww < kWaves; ww++) {
+                const uint32_t v = sc[ww][k];
+                before += ((uint32_t)ww < w) ? v : 0u;
+                round += v;
+            }
+            ex[k] += tot + before;  // newlines of the tile before this thread's bytes of round k
+            tot += round;
+        }
+        const uint64_t sbase = a.tile_base[t];
+#pragma unroll
+        for (int k = 0; k < kIdxRounds; k++) {
+            uint64_t k1 = sbase + ex[k];
+            const uint64_t x = tb + 4096u * k + 16u * tid;
+#pragma unroll
+            for (int q = 0; q < 4; q++) {
+                uint32_t m = mask[4 * k + q];
+                while (m) {
+                    const int bit = __builtin_ctz(m);
+                    m &= m - 1;
+                    k1++;
+                    if (k1 < a.off_cap) a.off[k1] = x + 4 * q + (bit >> 3) + 1;
                 }
             }
         }
@@ -1450,10 +1607,16 @@ DeviceInfo device_info() {
 }
 
 constexpr int kCompressWgPerCu = 4;  // upper bound of the persistent grid per CU (sizes the workspace)
-constexpr int kDecompressWgPerCu = 4;
+constexpr int kDecompressWgPerCu = 4;  // upper bound of the persistent grid per CU (sizes the workspace)
 constexpr int kIndexWgPerCu = 8;
 
 uint32_t tiles_for(uint64_t n, uint64_t per) { return (uint32_t)((n + per - 1) / per); }
+size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+// Jobs with at most this many tiles run as one decompression launch with a
+// look-back; larger ones as sizes -> scan -> emit.
+constexpr uint32_t kLookbackTiles = 1024;
+constexpr int kDecompressSizesWgPerCu = 8;
 
 size_t ws_bytes_for(int op, uint64_t n) {
     DeviceInfo di = device_info();
@@ -1467,10 +1630,14 @@ size_t ws_bytes_for(int op, uint64_t n) {
             return h + st + grid * kWG * kGenLane + grid * kSlotBytes;
         }
         case ZS_OP_DECOMPRESS:
-        case ZS_OP_DECOMPRESS_LINES:
-            return h + (size_t)tiles_for(n, kDL) * 8 + 64;
-        case ZS_OP_INDEX:
-            return h + (size_t)tiles_for(n, kIdxTile) * 8 + 64;
+        case ZS_OP_DECOMPRESS_LINES: {
+            const size_t nt = tiles_for(n, 32);  // tiles may be as small as 32 lines
+            return h + align256(nt * 8) + align256(nt * 4) + (nt + 1) * 8;
+        }
+        case ZS_OP_INDEX: {
+            const size_t nt = tiles_for(n, kIdxTile);
+            return h + align256(nt * 4) + (nt + 1) * 8;
+        }
         default:
             return 0;
     }
@@ -1633,11 +1800,19 @@ static zs_status decompress_common(const zs_dict* d, const uint8_t* in, uint64_t
     }
     DeviceInfo di = device_info();
     if (!di.ok) return ZS_EDEVICE;
-    const uint32_t ntiles = tiles_for(nreq, kDL);
+    // small request sets are cut into smaller tiles so that more workgroups share them
+    const uint64_t want = (uint64_t)di.cus * 2;
+    uint32_t tl = kDL;
+    while (tl > 32 && (nreq + tl - 1) / tl < want) tl >>= 1;
+    const uint32_t ntiles = tiles_for(nreq, tl);
+    const bool small = ntiles <= kLookbackTiles;
     WsHeader* h = (WsHeader*)ws;
     uint64_t* status = (uint64_t*)(h + 1);
-    if (launch_init(h, status, ntiles, (ResultOut*)res, s) != ZS_OK) return ZS_EDEVICE;
+    uint32_t* tile_total = (uint32_t*)((uint8_t*)status + align256((size_t)ntiles * 8));
+    uint64_t* tile_base = (uint64_t*)((uint8_t*)tile_total + align256((size_t)ntiles * 4));
+    if (launch_init(h, status, small ? ntiles : 0, (ResultOut*)res, s) != ZS_OK) return ZS_EDEVICE;
     DecompressArgs a;
+    a.tl = tl;
     a.tables = d->d_tables;
     a.in = in;
     a.in_bytes = in_bytes;
@@ -1651,10 +1826,30 @@ static zs_status decompress_common(const zs_dict* d, const uint8_t* in, uint64_t
     a.ntiles = ntiles;
     a.ws = h;
     a.status = status;
+    a.tile_total = tile_total;
+    a.tile_base = tile_base;
     a.res = (ResultOut*)res;
-    uint32_t grid = (uint32_t)di.cus * kDecompressWgPerCu;
-    if (grid > ntiles) grid = ntiles;
-    hipLaunchKernelGGL(decompress_kernel, dim3(grid), dim3(kWG), decompress_lds().total, s, a);
+    const DecompressLds dl = decompress_lds();
+    auto grid_for = [&](uint32_t lds, int cap) {
+        int occ = 0;
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, (const void*)decompress_kernel, kWG, lds) != hipSuccess ||
+            occ < 1)
+            occ = 1;
+        if (occ > cap) occ = cap;
+        uint32_t g = (uint32_t)di.cus * (uint32_t)occ;
+        return g > ntiles ? ntiles : g;
+    };
+    if (small) {
+        a.phase = kPhaseLookback;
+        hipLaunchKernelGGL(decompress_kernel, dim3(grid_for(dl.total, kDecompressWgPerCu)), dim3(kWG), dl.total, s, a);
+    } else {
+        a.phase = kPhaseSizes;
+        hipLaunchKernelGGL(decompress_kernel, dim3(grid_for(dl.total_sizes, kDecompressSizesWgPerCu)), dim3(kWG),
+                           dl.total_sizes, s, a);
+        hipLaunchKernelGGL(tile_scan_kernel, dim3(1), dim3(kScanWG), 0, s, tile_total, tile_base, ntiles);
+        a.phase = kPhaseEmit;
+        hipLaunchKernelGGL(decompress_kernel, dim3(grid_for(dl.total, kDecompressWgPerCu)), dim3(kWG), dl.total, s, a);
+    }
     return hipGetLastError() == hipSuccess ? ZS_OK : ZS_EDEVICE;
 }
 
@@ -1687,8 +1882,9 @@ zs_status zs_index_lines(const uint8_t* buf, uint64_t len, uint64_t* off, uint64
     if (!di.ok) return ZS_EDEVICE;
     const uint32_t ntiles = tiles_for(len, kIdxTile);
     WsHeader* h = (WsHeader*)ws;
-    uint64_t* status = (uint64_t*)(h + 1);
-    if (launch_init(h, status, ntiles, (ResultOut*)res, s) != ZS_OK) return ZS_EDEVICE;
+    uint32_t* tile_total = (uint32_t*)(h + 1);
+    uint64_t* tile_base = (uint64_t*)((uint8_t*)tile_total + align256((size_t)ntiles * 4));
+    if (launch_init(h, nullptr, 0, (ResultOut*)res, s) != ZS_OK) return ZS_EDEVICE;
     IndexArgs a;
     a.buf = buf;
     a.len = len;
@@ -1697,11 +1893,14 @@ zs_status zs_index_lines(const uint8_t* buf, uint64_t len, uint64_t* off, uint64
     a.n_lines_out = n_lines_out;
     a.ntiles = ntiles;
     a.ws = h;
-    a.status = status;
+    a.tile_total = tile_total;
+    a.tile_base = tile_base;
     a.res = (ResultOut*)res;
     uint32_t grid = (uint32_t)di.cus * kIndexWgPerCu;
     if (grid > ntiles) grid = ntiles;
-    hipLaunchKernelGGL(index_kernel, dim3(grid), dim3(kWG), 0, s, a);
+    hipLaunchKernelGGL(index_count_kernel, dim3(grid), dim3(kWG), 0, s, a);
+    hipLaunchKernelGGL(tile_scan_kernel, dim3(1), dim3(kScanWG), 0, s, tile_total, tile_base, ntiles);
+    hipLaunchKernelGGL(index_write_kernel, dim3(grid), dim3(kWG), 0, s, a);
     return hipGetLastError() == hipSuccess ? ZS_OK : ZS_EDEVICE;
 }
 

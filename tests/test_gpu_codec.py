@@ -206,6 +206,72 @@ def test_random_access(zs, gd, odict):
     assert zs.read_result(res) == (zs.EINVAL, 1)
 
 
+def _random_compressed(odict, n_lines, seed, p_esc=0.08, p_bad=0.0):
+    """Synthetic compressed lines: code bytes of the dictionary and escaped
+    literals (spaces included, so space runs of any length occur), a newline per
+    line; with p_bad, some tokens are undefined code bytes."""
+    rng = np.random.default_rng(seed)
+    codes = np.array(sorted(odict.entries), dtype=np.uint8)
+    undefined = np.array([c for c in range(0x21, 0x100) if c not in odict.entries and c != 0x7F], dtype=np.uint8)
+    ntok = rng.integers(0, 40, n_lines)
+    N = int(ntok.sum())
+    esc = rng.random(N) < p_esc
+    tok = rng.choice(codes, N)
+    if p_bad:
+        badt = rng.random(N) < p_bad
+        tok[badt] = rng.choice(undefined, int(badt.sum()))
+    lit = rng.integers(0x20, 0x7F, N).astype(np.uint8)
+    tlen = np.where(esc, 2, 1)
+    tok_line = np.repeat(np.arange(n_lines), ntok)
+    line_len = np.bincount(tok_line, weights=tlen, minlength=n_lines).astype(np.int64) + 1
+    off = np.zeros(n_lines + 1, dtype=np.uint64)
+    off[1:] = np.cumsum(line_len)
+    start = (np.cumsum(tlen) - tlen) + tok_line
+    buf = np.zeros(int(off[-1]), dtype=np.uint8)
+    buf[start] = np.where(esc, 0x20, tok)
+    buf[start[esc] + 1] = lit[esc]
+    buf[(off[1:] - 1).astype(np.int64)] = 0x0A
+    return buf, off
+
+
+def test_decompress_many_tiles(zs, gd, odict):
+    """More tiles than one look-back launch takes: sizes, scan of the tile totals, emit."""
+    buf, off = _random_compressed(odict, 400000, 81)
+    code, _ = _compare_decompress(zs, gd, odict, buf, off)
+    assert code == oracle.OK
+    b, o = dev(buf, off)
+    rnd = np.random.default_rng(82)
+    ids = rnd.integers(0, 400000, 300000).astype(np.uint64)
+    code, fb, want, woff = oracle.decompress_lines(odict, buf, off, ids)
+    got, goff = zs.decompress_lines(gd, b, o, torch.from_numpy(ids.astype(np.int64)).cuda())
+    assert np.array_equal(host(goff).astype(np.uint64), woff)
+    assert host(got).tobytes() == want.tobytes()
+
+
+@pytest.mark.parametrize("n", [3000, 400000])
+def test_decompress_corrupt_lines(zs, gd, odict, n):
+    """Undefined codes and dangling escapes spread over many lines: the bad lines
+    decode to empty lines, the first bad line is reported, every other line decodes."""
+    buf, off = _random_compressed(odict, n, 83 + n, p_bad=0.002)
+    # a dangling escape at the end of some lines
+    ends = (off[1:] - 2).astype(np.int64)
+    pick = ends[(np.arange(n) % 997 == 5) & (off[1:] - off[:-1] > 1)]
+    buf[pick] = 0x20
+    code, fb, want, woff = oracle.decompress(odict, buf, off)
+    assert code == oracle.ECORRUPT
+    b, o = dev(buf, off)
+    res = zs.new_result()
+    ws = zs.Workspaces().get(zs.OP_DECOMPRESS, n)
+    out_off = torch.empty(n + 1, dtype=torch.int64, device="cuda")
+    zs.decompress_into(gd, b, o, None, out_off, ws, res)
+    assert np.array_equal(host(out_off).astype(np.uint64), woff)
+    out = torch.empty(int(woff[-1]), dtype=torch.uint8, device="cuda")
+    res = zs.new_result()
+    zs.decompress_into(gd, b, o, out, out_off, ws, res)
+    assert zs.read_result(res) == (code, fb)
+    assert host(out).tobytes() == want.tobytes()
+
+
 def test_index_lines(zs, odict):
     for data in [b"", b"\n", b"CC", b"CC\n", b"CC\n\nC", b"\n\n\n"]:
         b = torch.from_numpy(np.frombuffer(data, dtype=np.uint8).copy()).cuda() if data else \
