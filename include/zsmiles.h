@@ -149,6 +149,60 @@ zs_status zs_decompress_lines(const zs_dict *d, const uint8_t *in, uint64_t in_b
 zs_status zs_index_lines(const uint8_t *buf, uint64_t len, uint64_t *off, uint64_t off_cap,
                          uint64_t *n_lines_out, void *ws, size_t ws_bytes, zs_result *res, void *stream);
 
+/*
+ * Length-binned compression, for batches whose line lengths are very uneven
+ * (the paper's compressor takes one block per SMILES, Sec. V; here lines are
+ * grouped by length so that the lanes of a wavefront hold lines of similar
+ * length).  On the device, the lines are sorted by raw length into cfg->nbins
+ * bins (a stable counting sort), every bin is compressed with its own tile
+ * shape, longest bin first, into a staging area of the workspace, and a last
+ * pass writes the lines back in input order.  The output (out, out_off, res)
+ * is identical to zs_compress's for every input; size-only mode and ENOSPC
+ * behave the same.  ws: at least zs_binned_workspace_bytes(n_lines, out_cap)
+ * bytes (it holds the staging copy of the output).
+ */
+#define ZS_MAX_BINS 8
+typedef struct {
+    uint32_t nbins;                        /* 1..ZS_MAX_BINS                                      */
+    uint32_t edges[ZS_MAX_BINS - 1];       /* ascending raw-length bounds: bin i holds lengths in */
+                                           /* [edges[i-1], edges[i]) (edges[-1] = 0, last open)   */
+    uint32_t lines_per_tile[ZS_MAX_BINS];  /* per bin, 1..256: lines (lanes) per workgroup tile   */
+    uint32_t large_lds[ZS_MAX_BINS];       /* per bin, 0 or 1: the LDS layout with the larger     */
+                                           /* line batch (2 workgroups per CU instead of 3)       */
+} zs_bin_config;
+
+size_t zs_binned_workspace_bytes(uint64_t n_lines, uint64_t out_cap);
+zs_status zs_compress_binned(const zs_dict *d, const uint8_t *in, uint64_t in_bytes, const uint64_t *in_off,
+                             uint64_t n_lines, uint8_t *out, uint64_t out_cap, uint64_t *out_off, uint32_t flags,
+                             const zs_bin_config *cfg, void *ws, size_t ws_bytes, zs_result *res, void *stream);
+
+/*
+ * Autotuner for zs_compress_binned: times a set of configurations (bin edges
+ * from the quantiles of the line lengths, lines per tile, LDS layout) on the
+ * given lines, which should be a sample of the workload, and returns the
+ * fastest in *best (and its time, ms, in *best_ms; the plain zs_compress time
+ * on the same lines in *plain_ms).  Unlike the compute calls it allocates
+ * device memory for its trials and synchronises; it runs on `stream`.
+ * n_tried receives the number of configurations timed.
+ */
+zs_status zs_autotune_binned(const zs_dict *d, const uint8_t *in, uint64_t in_bytes, const uint64_t *in_off,
+                             uint64_t n_lines, uint32_t flags, zs_bin_config *best, double *best_ms,
+                             double *plain_ms, uint32_t *n_tried, void *stream);
+
+/*
+ * HIP graphs of codec calls.  zs_graph_begin starts capturing the work that
+ * the following calls enqueue on `stream` (not the NULL stream);
+ * zs_graph_end stops and instantiates it.  zs_graph_launch replays the whole
+ * sequence with one launch; the captured calls read and write the same
+ * buffers on every replay.  Every kernel of the library may be captured (the
+ * library clears its counters with kernels, not memset nodes).
+ */
+typedef struct zs_graph zs_graph;
+zs_status zs_graph_begin(void *stream);
+zs_status zs_graph_end(void *stream, zs_graph **out);
+zs_status zs_graph_launch(zs_graph *g, void *stream);
+void zs_graph_destroy(zs_graph *g);
+
 /* Human-readable name of a status code. */
 const char *zs_status_str(int code);
 

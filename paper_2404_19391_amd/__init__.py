@@ -43,6 +43,34 @@ def default_dict_path():
     return os.path.join(_PKG, "data", "default.zsd")
 
 
+MAX_BINS = 8
+
+
+class BinConfig(ctypes.Structure):
+    """zs_bin_config: bins by raw line length (ascending edges), lines per tile and LDS layout per bin."""
+    _fields_ = [("nbins", ctypes.c_uint32), ("edges", ctypes.c_uint32 * (MAX_BINS - 1)),
+                ("lines_per_tile", ctypes.c_uint32 * MAX_BINS), ("large_lds", ctypes.c_uint32 * MAX_BINS)]
+
+    @classmethod
+    def make(cls, edges=(), lines_per_tile=None, large_lds=None):
+        c = cls()
+        c.nbins = len(edges) + 1
+        for i, e in enumerate(edges):
+            c.edges[i] = int(e)
+        lpt = list(lines_per_tile) if lines_per_tile is not None else [256] * c.nbins
+        lg = list(large_lds) if large_lds is not None else [0] * c.nbins
+        for i in range(c.nbins):
+            c.lines_per_tile[i] = int(lpt[i])
+            c.large_lds[i] = int(lg[i])
+        return c
+
+    def as_dict(self):
+        n = int(self.nbins)
+        return {"nbins": n, "edges": [int(self.edges[i]) for i in range(n - 1)],
+                "lines_per_tile": [int(self.lines_per_tile[i]) for i in range(n)],
+                "large_lds": [int(self.large_lds[i]) for i in range(n)]}
+
+
 def lib():
     """The loaded libzsmiles.so; raises if it has not been built."""
     global _lib
@@ -74,6 +102,23 @@ def lib():
                                           ctypes.c_size_t, _vp, _vp]
         L.zs_index_lines.restype = ctypes.c_int
         L.zs_index_lines.argtypes = [_vp, _u64, _vp, _u64, _vp, _vp, ctypes.c_size_t, _vp, _vp]
+        L.zs_binned_workspace_bytes.restype = ctypes.c_size_t
+        L.zs_binned_workspace_bytes.argtypes = [_u64, _u64]
+        L.zs_compress_binned.restype = ctypes.c_int
+        L.zs_compress_binned.argtypes = [_vp, _vp, _u64, _vp, _u64, _vp, _u64, _vp, ctypes.c_uint32,
+                                         ctypes.POINTER(BinConfig), _vp, ctypes.c_size_t, _vp, _vp]
+        L.zs_autotune_binned.restype = ctypes.c_int
+        L.zs_autotune_binned.argtypes = [_vp, _vp, _u64, _vp, _u64, ctypes.c_uint32, ctypes.POINTER(BinConfig),
+                                         ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double),
+                                         ctypes.POINTER(ctypes.c_uint32), _vp]
+        L.zs_graph_begin.restype = ctypes.c_int
+        L.zs_graph_begin.argtypes = [_vp]
+        L.zs_graph_end.restype = ctypes.c_int
+        L.zs_graph_end.argtypes = [_vp, ctypes.POINTER(_vp)]
+        L.zs_graph_launch.restype = ctypes.c_int
+        L.zs_graph_launch.argtypes = [_vp, _vp]
+        L.zs_graph_destroy.restype = None
+        L.zs_graph_destroy.argtypes = [_vp]
         L.zsi_compile_dict_c.restype = ctypes.c_int
         L.zsi_compile_dict_c.argtypes = [_vp, _vp, _vp, _u64, ctypes.POINTER(_u64)]
         _lib = L
@@ -238,6 +283,72 @@ def compress_into(d, buf, off, out, out_off, ws, res, preprocess=True, in_bytes=
     _check_rc(rc, "zs_compress")
 
 
+def binned_workspace_bytes(n, out_cap):
+    return int(lib().zs_binned_workspace_bytes(n, out_cap))
+
+
+def compress_binned_into(d, buf, off, out, out_off, cfg, ws, res, preprocess=True, in_bytes=None):
+    """zs_compress_binned on preallocated tensors; out may be None (size-only)."""
+    n = off.numel() - 1
+    nb = buf.numel() if in_bytes is None else in_bytes
+    rc = lib().zs_compress_binned(d.handle, _p(buf), nb, _p(off), n, _p(out),
+                                  out.numel() if out is not None else 0, _p(out_off),
+                                  F_PREPROCESS if preprocess else 0, ctypes.byref(cfg), _p(ws), ws.numel(), _p(res),
+                                  _stream())
+    _check_rc(rc, "zs_compress_binned")
+
+
+def autotune_binned(d, buf, off, preprocess=True):
+    """zs_autotune_binned on device lines (a sample of the workload): (BinConfig, best_ms, plain_ms, tried)."""
+    n = off.numel() - 1
+    cfg = BinConfig()
+    best, plain = ctypes.c_double(0), ctypes.c_double(0)
+    tried = ctypes.c_uint32(0)
+    rc = lib().zs_autotune_binned(d.handle, _p(buf), buf.numel(), _p(off), n, F_PREPROCESS if preprocess else 0,
+                                  ctypes.byref(cfg), ctypes.byref(best), ctypes.byref(plain), ctypes.byref(tried),
+                                  _stream())
+    _check_rc(rc, "zs_autotune_binned")
+    return cfg, best.value, plain.value, int(tried.value)
+
+
+class Graph:
+    """A HIP graph of codec calls: capture the calls made inside `with g.capture(stream):`, then replay()."""
+
+    def __init__(self):
+        self.handle = None
+        self.stream = None
+
+    def capture(self, stream):
+        g = self
+
+        class _Ctx:
+            def __enter__(self_):
+                g.stream = stream
+                _check_rc(lib().zs_graph_begin(_vp(stream.cuda_stream)), "zs_graph_begin")
+                return g
+
+            def __exit__(self_, et, ev, tb):
+                h = _vp()
+                rc = lib().zs_graph_end(_vp(stream.cuda_stream), ctypes.byref(h))
+                if et is None:
+                    _check_rc(rc, "zs_graph_end")
+                    g.handle = h
+                return False
+
+        return _Ctx()
+
+    def replay(self, stream=None):
+        s = stream if stream is not None else self.stream
+        _check_rc(lib().zs_graph_launch(self.handle, _vp(s.cuda_stream)), "zs_graph_launch")
+
+    def __del__(self):
+        try:
+            if self.handle:
+                lib().zs_graph_destroy(self.handle)
+        except Exception:
+            pass
+
+
 def decompress_into(d, buf, off, out, out_off, ws, res, in_bytes=None):
     n = off.numel() - 1
     nb = buf.numel() if in_bytes is None else in_bytes
@@ -284,6 +395,25 @@ def compress(d, buf, off, preprocess=True, check=True):
     ws = _ws_for(dev).get(OP_COMPRESS, n)
     return _sized(lambda out, res: compress_into(d, buf, off, out, out_off, ws, res, preprocess), out_off, dev,
                   check, "compress")
+
+
+def compress_binned(d, buf, off, cfg, preprocess=True, check=True):
+    """Length-binned compression; the same bytes and offsets as compress()."""
+    torch = _torch()
+    n = off.numel() - 1
+    dev = buf.device if buf.numel() else off.device
+    out_off = torch.empty(n + 1, dtype=torch.int64, device=dev)
+    state = {}
+
+    def run(out, res):
+        cap = out.numel() if out is not None else 0
+        need = max(binned_workspace_bytes(n, cap), 64)
+        ws = state.get("ws")
+        if ws is None or ws.numel() < need:
+            ws = state["ws"] = torch.empty(need, dtype=torch.uint8, device=dev)
+        compress_binned_into(d, buf, off, out, out_off, cfg, ws, res, preprocess)
+
+    return _sized(run, out_off, dev, check, "compress_binned")
 
 
 def decompress(d, buf, off, check=True):

@@ -166,18 +166,19 @@ __device__ inline uint32_t claim_tile(WsHeader* h, uint32_t* s_slot) {
     return t;
 }
 
-// The last workgroup to finish writes the result word.  res may be null.
+// The last workgroup to finish writes the result word from h's error state.
+// res may be null; the finishing count is kept in hdone (default: h).
 struct ResultOut {
     int32_t code;
     int32_t reserved;
     int64_t first_bad;
 };
 
-__device__ inline void finish_workgroup(WsHeader* h, ResultOut* res, uint32_t nblocks) {
+__device__ inline void finish_workgroup(WsHeader* h, ResultOut* res, uint32_t nblocks, WsHeader* hdone = nullptr) {
     __syncthreads();
     if (threadIdx.x == 0) {
         __threadfence();
-        uint32_t prev = atomicAdd(&h->done, 1u);
+        uint32_t prev = atomicAdd(&(hdone ? hdone : h)->done, 1u);
         if (prev == nblocks - 1) {
             __threadfence();
             uint64_t ek = __hip_atomic_load(&h->errkey, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);

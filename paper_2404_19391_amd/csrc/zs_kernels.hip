@@ -24,7 +24,10 @@
 #include <stdint.h>
 #include <string.h>
 
+#include <algorithm>
 #include <mutex>
+#include <new>
+#include <stddef.h>
 #include <vector>
 
 #include "../../include/zsmiles.h"
@@ -41,14 +44,18 @@ namespace {
 // Compression
 // ============================================================================
 
-constexpr int kCL = 256;              // lines per tile (one per thread)
-constexpr int kRawCap = 14336;        // LDS bytes for the raw lines of a batch; reused as output stage
-constexpr int kPreCap = 14336;        // LDS bytes for their pre-processed form
+constexpr int kCL = 256;              // lines per tile at most (one per thread)
+// LDS bytes of a batch's raw lines (reused as output stage) and, as many, of
+// their pre-processed form: the default variant runs 3 workgroups per CU, the
+// large one (long lines) 2.
+constexpr int kCapSmall = 14336;
+constexpr int kCapLarge = 26624;
 constexpr int kSlots = 8;             // fast ring tables (registers): open rings, slot = label % 8
 constexpr int kGenLane = 400;         // per-lane ring tables in global memory (any line):
                                       // 100 open positions u16 + 100 last-close u16
-static_assert(kPreCap >= 3 * (int)ZS_MAX_LINE, "a pre-processed line must fit");
-static_assert(kRawCap >= (int)ZS_MAX_LINE + 1 + 16, "a raw line must fit");
+static_assert(kCapSmall >= 3 * (int)ZS_MAX_LINE, "a pre-processed line must fit");
+static_assert(kCapSmall >= (int)ZS_MAX_LINE + 1 + 16, "a raw line must fit");
+constexpr uint64_t kAbsBad = 1ull << 63;  // ABS flag (binned mode): the line's framing is bad
 
 constexpr uint8_t kSkip = 0x7F;    // marker: byte dropped by pre-processing
 constexpr uint8_t kIdMark = 0x80;  // marker: ring-label with ID (low 7 bits)
@@ -56,18 +63,19 @@ constexpr uint32_t kBadLine = 0x8000u;  // LENS flag: the line is bad (empty out
 
 struct CompressLds {
     uint32_t tab_bytes;  // dictionary part staged
-    uint32_t raw, pre, esc, off, cost, eoff, lens, perm, misc;
+    uint32_t raw, pre, esc, off, abs, cost, eoff, lens, perm, misc;
     uint32_t total;
 };
 
-__host__ __device__ inline CompressLds compress_lds(uint32_t tab_bytes) {
+__host__ __device__ inline CompressLds compress_lds(uint32_t tab_bytes, uint32_t cap) {
     CompressLds L;
     L.tab_bytes = align16(tab_bytes);
     uint32_t o = L.tab_bytes;
-    L.raw = o;  o += kRawCap;
-    L.pre = o;  o += kPreCap;
-    L.esc = o;  o += kPreCap / 8;
+    L.raw = o;  o += cap;
+    L.pre = o;  o += cap;
+    L.esc = o;  o += cap / 8;
     L.off = o;  o += align16((kCL + 1) * 8);
+    L.abs = o;  o += align16(kCL * 8);
     L.cost = o; o += kCL * 4;
     L.eoff = o; o += kCL * 4;
     L.lens = o; o += kCL * 2;
@@ -76,6 +84,19 @@ __host__ __device__ inline CompressLds compress_lds(uint32_t tab_bytes) {
     L.total = align16(o);
     return L;
 }
+
+// Tile geometry of the length bins (binned mode), written on the device.
+// Bins are numbered in the order they are processed: longest lines first.
+constexpr int kMaxBins = 8;
+struct BinPlan {
+    uint32_t nbins;
+    uint32_t upper[kMaxBins];          // bin b holds lines of raw length < upper[b] (and >= upper[b + 1])
+    uint32_t lpt[kMaxBins];            // lines per tile of bin b
+    uint32_t count[kMaxBins];          // lines in bin b
+    uint64_t start[kMaxBins];          // first position of bin b in the id order
+    uint32_t first_tile[kMaxBins + 1]; // global index of bin b's first tile; [nbins] = all tiles
+    uint32_t ticket[kMaxBins];         // per-launch tile counters
+};
 
 struct CompressArgs {
     const uint8_t* tables;  // device image
@@ -92,11 +113,14 @@ struct CompressArgs {
     WsHeader* ws;
     uint64_t* status;
     uint8_t* gen;           // general ring tables, kGenLane bytes per (workgroup, lane)
-    uint8_t* slots;         // kSlotBytes per workgroup: a finished tile waiting for its offset
+    uint8_t* slots;         // CAP bytes per workgroup: a finished tile waiting for its offset
     ResultOut* res;
+    // binned mode (null ids: plain mode, tile t = lines [256 t, 256 t + 256))
+    const uint32_t* ids;    // line ids in bin order
+    const struct BinPlan* plan;
+    uint32_t bin_lo, bin_hi;  // the bins this launch takes
+    uint32_t* ticket;       // this launch's tile counter
 };
-
-constexpr int kSlotBytes = kRawCap;  // a deferred tile's output fits one stage window
 
 __device__ inline bool is_digit(uint32_t c) { return c - '0' < 10u; }
 
@@ -161,8 +185,9 @@ __device__ inline bool ring_general(uint8_t* raw, uint32_t R, uint32_t len, uint
     return opens == 0;
 }
 
-template <int LK>
+template <int LK, int CAP>
 struct Compressor {
+    static constexpr int kRawCap = CAP, kPreCap = CAP, kSlotBytes = CAP;
     const CompressArgs A;
     uint8_t* smem;
     CompressLds L;
@@ -175,7 +200,7 @@ struct Compressor {
     uint32_t C;  // automaton columns
 
     __device__ Compressor(const CompressArgs& a, uint8_t* s) : A(a), smem(s) {
-        L = compress_lds(a.tab_bytes);
+        L = compress_lds(a.tab_bytes, CAP);
         H = (const TableHeader*)smem;
         LENT = smem + H->off_len;
         COL = smem + H->off_col;
@@ -187,6 +212,7 @@ struct Compressor {
     }
 
     __device__ __forceinline__ uint64_t* OFF() { return (uint64_t*)(smem + L.off); }
+    __device__ __forceinline__ uint64_t* ABS() { return (uint64_t*)(smem + L.abs); }
     __device__ __forceinline__ uint32_t* COST() { return (uint32_t*)(smem + L.cost); }
     __device__ __forceinline__ uint32_t* EOFF() { return (uint32_t*)(smem + L.eoff); }
     __device__ __forceinline__ uint16_t* LENS() { return (uint16_t*)(smem + L.lens); }
@@ -196,8 +222,16 @@ struct Compressor {
     __device__ __forceinline__ uint8_t* PRE() { return smem + L.pre; }
     __device__ __forceinline__ uint32_t* ESC() { return (uint32_t*)(smem + L.esc); }
 
+    // Index of line j of the tile in the input (binned mode: from the id list).
+    __device__ __forceinline__ uint64_t line_id(uint64_t k0, uint32_t j) { return A.ids ? A.ids[k0 + j] : k0 + j; }
+    // Input bytes of line j of the tile.
+    __device__ __forceinline__ const uint8_t* line_src(uint32_t j) {
+        return A.in + (A.ids ? (ABS()[j] & ~kAbsBad) : OFF()[j]);
+    }
+
     // Framing of line j of the tile (OFF staged).  0 = ok, else error kind.
     __device__ __forceinline__ uint32_t frame_error(uint64_t k0, uint32_t j) {
+        if (A.ids) return (ABS()[j] & kAbsBad) ? kErrInval : 0u;
         const uint64_t a = OFF()[j], b = OFF()[j + 1];
         if (b <= a || b > A.in_bytes + 1) return kErrInval;
         if (b - a - 1 > ZS_MAX_LINE) return kErrInval;
@@ -399,6 +433,45 @@ struct Compressor {
         }
     }
 
+    // Binned mode: copy lines [b0, b1) of the tile to RAW at their packed
+    // offsets OFF - OFF[b0].  Each thread fills 16-byte pieces of RAW; the line
+    // of a piece comes from a search of OFF.  A bad line is a lone newline;
+    // a virtual final newline is not in memory.
+    __device__ __forceinline__ void load_gather(uint32_t b0, uint32_t b1, uint8_t* raw) {
+        const uint64_t* off = OFF();
+        const uint64_t* abs = ABS();
+        const uint32_t lo = (uint32_t)off[b0], n = (uint32_t)off[b1] - lo;
+        for (uint32_t r0 = threadIdx.x * 16; r0 < n; r0 += kWG * 16) {
+            uint32_t l = b0, h = b1;
+            while (h - l > 1) {
+                const uint32_t mid = (l + h) >> 1;
+                if ((uint32_t)off[mid] - lo <= r0) l = mid;
+                else h = mid;
+            }
+            uint32_t q = l;
+            uint32_t qs = (uint32_t)off[q] - lo, qe = (uint32_t)off[q + 1] - lo;
+            uint8_t v[16];
+#pragma unroll
+            for (int k = 0; k < 16; k++) {
+                const uint32_t r = r0 + k;
+                v[k] = 0;
+                if (r < n) {
+                    while (r >= qe) {
+                        q++;
+                        qs = qe;
+                        qe = (uint32_t)off[q + 1] - lo;
+                    }
+                    const uint64_t a = abs[q];
+                    if (r + 1 == qe && ((a & kAbsBad) || (a & ~kAbsBad) + (qe - qs) == A.in_bytes + 1)) v[k] = '\n';
+                    else if (!(a & kAbsBad)) v[k] = A.in[(a & ~kAbsBad) + (r - qs)];
+                }
+            }
+#pragma unroll
+            for (int k = 0; k < 16; k++)
+                if (r0 + k < n) raw[r0 + k] = v[k];
+        }
+    }
+
     // Process lines [b0, ...) of the tile as one batch: load, ring IDs, expand,
     // parse.  Fills COST for the batch lines and returns b1.  The per-lane
     // state needed for emission is left in `st`.
@@ -430,14 +503,19 @@ struct Compressor {
             // ---- load
             const uint32_t fe0 = frame_error(k0, b0);
             const uint64_t lo = off[b0];
-            uint64_t hi = off[b1];
-            if (hi > A.in_bytes) hi = A.in_bytes;
-            const uintptr_t a0 = ((uintptr_t)(A.in + lo)) & ~(uintptr_t)15;
-            const uint32_t base_off = (uint32_t)((uintptr_t)(A.in + lo) - a0);
-            if (fe0 == 0) load_range(A.in, A.in_bytes, lo, hi, a0, raw);
-            __syncthreads();
-            if (tid == 0 && fe0 == 0 && off[b1] == A.in_bytes + 1)
-                raw[(uint32_t)(off[b1] - 1 - lo) + base_off] = '\n';
+            uint32_t base_off = 0;
+            if (A.ids) {
+                load_gather(b0, b1, raw);
+            } else {
+                uint64_t hi = off[b1];
+                if (hi > A.in_bytes) hi = A.in_bytes;
+                const uintptr_t a0 = ((uintptr_t)(A.in + lo)) & ~(uintptr_t)15;
+                base_off = (uint32_t)((uintptr_t)(A.in + lo) - a0);
+                if (fe0 == 0) load_range(A.in, A.in_bytes, lo, hi, a0, raw);
+                __syncthreads();
+                if (tid == 0 && fe0 == 0 && off[b1] == A.in_bytes + 1)
+                    raw[(uint32_t)(off[b1] - 1 - lo) + base_off] = '\n';
+            }
             __syncthreads();
             // ---- framing per line, lengths for the rank order
             if (tid < nb) {
@@ -448,7 +526,7 @@ struct Compressor {
                     len = (uint32_t)(off[j + 1] - off[j] - 1);
                     if (raw[(uint32_t)(off[j] - lo) + base_off + len] != '\n') fe = kErrInval;
                 }
-                if (fe) note_error(A.ws, k0 + j, fe);
+                if (fe) note_error(A.ws, line_id(k0, j), fe);
                 lens[tid] = fe ? (uint16_t)kBadLine : (uint16_t)len;
             }
             __syncthreads();
@@ -497,7 +575,7 @@ struct Compressor {
                 scan_labels(raw, st.R, st.len, list, st.len >> 1, &nlab, &corrupt, &malformed, &over, &pct);
                 if (corrupt) {
                     st.bad = true;
-                    note_error(A.ws, k0 + line, kErrCorrupt);
+                    note_error(A.ws, line_id(k0, line), kErrCorrupt);
                 } else if (prep && !malformed) {
                     if (over) overflow = true;
                     else run_rings = true;
@@ -512,15 +590,15 @@ struct Compressor {
                 const bool ok = ring_fast(raw, st.R, list, nlab, maxlab, &delta, &overflow, &marked);
                 if (!ok && !overflow) {
                     malformed = true;
-                    restore_line(raw, st.R, A.in + off[line], st.len);
+                    restore_line(raw, st.R, line_src(line), st.len);
                 }
             }
             if (overflow) {
-                restore_line(raw, st.R, A.in + off[line], st.len);
+                restore_line(raw, st.R, line_src(line), st.len);
                 uint16_t* open = (uint16_t*)(A.gen + ((uint64_t)blockIdx.x * kWG + tid) * kGenLane);
                 if (!ring_general(raw, st.R, st.len, open, open + 100, &delta)) {
                     malformed = true;
-                    restore_line(raw, st.R, A.in + off[line], st.len);
+                    restore_line(raw, st.R, line_src(line), st.len);
                 } else {
                     marked = true;
                 }
@@ -674,22 +752,62 @@ struct Compressor {
         uint32_t pt = 0, pnl = 0, ptotal = 0;
         uint64_t pk0 = 0;
         while (true) {
-            const uint32_t t = claim_tile(A.ws, &misc[2]);
-            const bool have = t < A.ntiles;
+            uint32_t t, nl = 0;
+            uint64_t k0 = 0;
+            bool have;
+            if (A.ids) {
+                // binned mode: this launch's tiles are [first_tile[bin_lo], first_tile[bin_hi])
+                if (tid == 0) misc[2] = atomicAdd(A.ticket, 1u);
+                __syncthreads();
+                t = A.plan->first_tile[A.bin_lo] + misc[2];
+                __syncthreads();
+                have = t < A.plan->first_tile[A.bin_hi];
+                if (have) {
+                    uint32_t b = A.bin_lo;
+                    while (t >= A.plan->first_tile[b + 1]) b++;
+                    const uint32_t lpt = A.plan->lpt[b];
+                    k0 = A.plan->start[b] + (uint64_t)(t - A.plan->first_tile[b]) * lpt;
+                    nl = (uint32_t)min((uint64_t)lpt, A.plan->start[b] + A.plan->count[b] - k0);
+                }
+            } else {
+                t = claim_tile(A.ws, &misc[2]);
+                have = t < A.ntiles;
+                if (have) {
+                    k0 = (uint64_t)t * kCL;
+                    nl = (uint32_t)min((uint64_t)kCL, A.n - k0);
+                }
+            }
             LineState st;
             st.simple = true;
             st.in = false;
             st.bad = false;
-            uint32_t nb = 0, nl = 0, total = 0, e = 0, mylen = 0;
-            uint64_t k0 = 0;
+            uint32_t nb = 0, total = 0, e = 0, mylen = 0;
             bool regular = true;
             if (have) {
-                k0 = (uint64_t)t * kCL;
-                nl = (uint32_t)min((uint64_t)kCL, A.n - k0);
-                for (uint32_t j = tid; j <= nl; j += kWG) off[j] = A.in_off[k0 + j];
+                if (A.ids) {
+                    // packed offsets of the gathered lines; a bad line takes one byte
+                    uint64_t a = 0;
+                    uint32_t sz = 0;
+                    if (tid < nl) {
+                        const uint64_t id = A.ids[k0 + tid];
+                        a = A.in_off[id];
+                        const uint64_t b = A.in_off[id + 1];
+                        bool bad = b <= a || b > A.in_bytes + 1 || b - a - 1 > ZS_MAX_LINE ||
+                                   (b == A.in_bytes + 1 && id + 1 != A.n);
+                        sz = bad ? 1u : (uint32_t)(b - a);
+                        if (bad) a |= kAbsBad;
+                        ABS()[tid] = a;
+                    }
+                    uint32_t tot;
+                    const uint32_t ex = block_excl_scan(sz, misc + 4, &tot);
+                    if (tid < nl) off[tid] = ex;
+                    if (tid == 0) off[nl] = tot;
+                } else {
+                    for (uint32_t j = tid; j <= nl; j += kWG) off[j] = A.in_off[k0 + j];
+                }
                 if (tid < kCL) COST()[tid] = 0;
                 __syncthreads();
-                regular = __syncthreads_and(tid >= nl || frame_error(k0, tid) == 0) != 0;
+                regular = A.ids != nullptr || __syncthreads_and(tid >= nl || frame_error(k0, tid) == 0) != 0;
                 // sweep 1: parse every batch, sizes into COST
                 uint32_t b0 = 0;
                 while (b0 < nl) {
@@ -762,7 +880,7 @@ struct Compressor {
     }
 };
 
-template <int LK>
+template <int LK, int CAP>
 __global__ void __launch_bounds__(kWG) compress_kernel(CompressArgs a) {
     extern __shared__ __align__(16) uint8_t smem[];
     // stage the dictionary image (up to EXP) in LDS
@@ -772,7 +890,7 @@ __global__ void __launch_bounds__(kWG) compress_kernel(CompressArgs a) {
         for (uint32_t k = threadIdx.x; k < a.tab_bytes / 16; k += kWG) dst[k] = src[k];
     }
     __syncthreads();
-    Compressor<LK> c(a, smem);
+    Compressor<LK, CAP> c(a, smem);
     c.run();
 }
 
@@ -1407,6 +1525,275 @@ __global__ void __launch_bounds__(kScanWG) tile_scan_kernel(const uint32_t* tota
 }
 
 // ============================================================================
+// Length-binned compression: device-side binning and placement
+// ============================================================================
+
+constexpr int kBinChunk = 4096;  // lines per workgroup of the binning kernels
+
+// Processing-order bin of a line of raw length len (bad framing: the last bin).
+__device__ inline uint32_t bin_of(const BinPlan* plan, uint64_t a, uint64_t b, uint64_t in_bytes) {
+    const uint32_t nb = plan->nbins;
+    if (b <= a || b > in_bytes + 1) return nb - 1;
+    const uint64_t len = b - a - 1;
+    uint32_t k = 0;
+    for (uint32_t i = 0; i < nb; i++) k += (uint64_t)plan->upper[i] > len ? 1u : 0u;
+    return k == 0 ? 0u : k - 1;
+}
+
+struct BinArgs {
+    const uint64_t* in_off;
+    uint64_t n;
+    uint64_t in_bytes;
+    BinPlan* plan;
+    uint32_t* hist;  // [chunk][kMaxBins]: counts, then (after the plan kernel) first positions
+    uint32_t nchunks;
+    uint32_t* ids;     // line ids in bin order
+    uint32_t* pos_of;  // position of each line in that order
+};
+
+// Counts of each bin per chunk of kBinChunk lines.
+__global__ void __launch_bounds__(kWG) bin_count_kernel(BinArgs a) {
+    __shared__ uint32_t cnt[kMaxBins];
+    for (uint32_t c = blockIdx.x; c < a.nchunks; c += gridDim.x) {
+        if (threadIdx.x < kMaxBins) cnt[threadIdx.x] = 0;
+        __syncthreads();
+        const uint64_t k0 = (uint64_t)c * kBinChunk;
+        const uint64_t k1 = min(a.n, k0 + kBinChunk);
+        for (uint64_t k = k0 + threadIdx.x; k < k1; k += kWG)
+            atomicAdd(&cnt[bin_of(a.plan, a.in_off[k], a.in_off[k + 1], a.in_bytes)], 1u);
+        __syncthreads();
+        if (threadIdx.x < kMaxBins) a.hist[(size_t)c * kMaxBins + threadIdx.x] = cnt[threadIdx.x];
+        __syncthreads();
+    }
+}
+
+// One workgroup: bin sizes and starts, each chunk's first position per bin,
+// the tiles of every bin.
+__global__ void __launch_bounds__(kWG) bin_plan_kernel(BinArgs a) {
+    __shared__ uint32_t sc[kWaves + 1];
+    __shared__ uint64_t bin_total[kMaxBins];
+    BinPlan* plan = a.plan;
+    const uint32_t tid = threadIdx.x;
+    const uint32_t per = (a.nchunks + kWG - 1) / kWG;
+    const uint32_t c0 = min(a.nchunks, tid * per), c1 = min(a.nchunks, c0 + per);
+    // exclusive scan over the chunks, bin by bin (positions inside the bin)
+    for (uint32_t b = 0; b < plan->nbins; b++) {
+        uint32_t s = 0;
+        for (uint32_t c = c0; c < c1; c++) s += a.hist[(size_t)c * kMaxBins + b];
+        uint32_t tot;
+        uint32_t run = block_excl_scan(s, sc, &tot);
+        for (uint32_t c = c0; c < c1; c++) {
+            const uint32_t v = a.hist[(size_t)c * kMaxBins + b];
+            a.hist[(size_t)c * kMaxBins + b] = run;
+            run += v;
+        }
+        if (tid == 0) bin_total[b] = tot;
+        __syncthreads();
+    }
+    if (tid == 0) {
+        uint64_t start = 0;
+        uint32_t tiles = 0;
+        for (uint32_t b = 0; b < plan->nbins; b++) {
+            plan->start[b] = start;
+            plan->count[b] = (uint32_t)bin_total[b];
+            plan->first_tile[b] = tiles;
+            start += bin_total[b];
+            tiles += (uint32_t)((bin_total[b] + plan->lpt[b] - 1) / plan->lpt[b]);
+        }
+        plan->first_tile[plan->nbins] = tiles;
+    }
+    __syncthreads();
+    // chunk positions become absolute
+    for (uint32_t b = 0; b < plan->nbins; b++) {
+        const uint32_t st = (uint32_t)plan->start[b];
+        for (uint32_t c = c0; c < c1; c++) a.hist[(size_t)c * kMaxBins + b] += st;
+    }
+}
+
+// Stable scatter of the line ids into bin order (rank inside a wave from a
+// ballot per bin, waves in order through LDS).
+__global__ void __launch_bounds__(kWG) bin_scatter_kernel(BinArgs a) {
+    __shared__ uint32_t wcnt[kWaves][kMaxBins];
+    __shared__ uint32_t run[kMaxBins];
+    const uint32_t tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+    const uint64_t below = lane ? (~0ull >> (64 - lane)) : 0ull;
+    const uint32_t nb = a.plan->nbins;
+    for (uint32_t c = blockIdx.x; c < a.nchunks; c += gridDim.x) {
+        if (tid < kMaxBins) run[tid] = a.hist[(size_t)c * kMaxBins + tid];
+        __syncthreads();
+        const uint64_t k0 = (uint64_t)c * kBinChunk;
+        const uint64_t k1 = min(a.n, k0 + kBinChunk);
+        for (uint64_t r = k0; r < k1; r += kWG) {
+            const uint64_t k = r + tid;
+            const bool in = k < k1;
+            const uint32_t bin = in ? bin_of(a.plan, a.in_off[k], a.in_off[k + 1], a.in_bytes) : kMaxBins;
+            uint32_t rank = 0;
+            for (uint32_t b = 0; b < nb; b++) {
+                const uint64_t m = __ballot(bin == b);
+                if (bin == b) rank = (uint32_t)__popcll(m & below);
+                if (lane == 0) wcnt[w][b] = (uint32_t)__popcll(m);
+            }
+            __syncthreads();
+            if (in) {
+                uint32_t pos = run[bin] + rank;
+                for (uint32_t ww = 0; ww < w; ww++) pos += wcnt[ww][bin];
+                a.ids[pos] = (uint32_t)k;
+                a.pos_of[k] = pos;
+            }
+            __syncthreads();
+            if (tid < nb) {
+                uint32_t s = 0;
+                for (int ww = 0; ww < kWaves; ww++) s += wcnt[ww][tid];
+                run[tid] += s;
+            }
+            __syncthreads();
+        }
+    }
+}
+
+struct PlaceArgs {
+    const uint32_t* pos_of;
+    const uint64_t* soff;   // staging offsets in bin order (n + 1 entries)
+    const uint8_t* staging;
+    uint64_t n;
+    uint8_t* out;
+    uint64_t out_cap;
+    uint64_t* out_off;
+    uint32_t ntiles;
+    uint32_t* tile_total;
+    const uint64_t* tile_base;
+    WsHeader* ws;      // errors and ENOSPC (shared with the compression launches)
+    WsHeader* done;    // this kernel's finishing counter
+    ResultOut* res;
+};
+
+// Output bytes per tile of kCL lines in input order.
+__global__ void __launch_bounds__(kWG) place_count_kernel(PlaceArgs a) {
+    __shared__ uint32_t sc[kWaves];
+    const uint32_t tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+    for (uint32_t t = blockIdx.x; t < a.ntiles; t += gridDim.x) {
+        const uint64_t k = (uint64_t)t * kCL + tid;
+        uint32_t len = 0;
+        if (k < a.n) {
+            const uint32_t p = a.pos_of[k];
+            len = (uint32_t)(a.soff[p + 1] - a.soff[p]);
+        }
+        const uint32_t s = (uint32_t)wave_sum64(len);
+        if (lane == 0) sc[w] = s;
+        __syncthreads();
+        if (tid == 0) a.tile_total[t] = sc[0] + sc[1] + sc[2] + sc[3];
+        __syncthreads();
+    }
+}
+
+// Offsets in input order, and the lines' bytes from the staging area: each
+// thread builds 16 bytes of the destination's 16-byte grid (the line of each
+// byte from a search of the tile's line starts) and stores them at once.
+__global__ void __launch_bounds__(kWG) place_write_kernel(PlaceArgs a) {
+    __shared__ uint32_t e[kCL + 1];
+    __shared__ uint64_t src[kCL];
+    __shared__ uint32_t sc[kWaves + 1];
+    const uint32_t tid = threadIdx.x;
+    for (uint32_t t = blockIdx.x; t < a.ntiles; t += gridDim.x) {
+        const uint64_t k0 = (uint64_t)t * kCL;
+        const uint32_t nl = (uint32_t)min((uint64_t)kCL, a.n - k0);
+        uint32_t len = 0;
+        if (tid < nl) {
+            const uint32_t p = a.pos_of[k0 + tid];
+            src[tid] = a.soff[p];
+            len = (uint32_t)(a.soff[p + 1] - a.soff[p]);
+        }
+        uint32_t tot;
+        const uint32_t ex = block_excl_scan(len, sc, &tot);
+        const uint64_t base = a.tile_base[t];
+        if (tid < nl) {
+            e[tid] = ex;
+            a.out_off[k0 + tid + 1] = base + ex + len;
+        }
+        if (tid == 0) {
+            e[nl] = tot;
+            if (t == 0) a.out_off[0] = 0;
+        }
+        __syncthreads();
+        const bool fits = base + tot <= a.out_cap;
+        if (!fits && tid == 0) atomicOr(&a.ws->enospc, 1u);
+        if (a.out && fits && tot) {
+            const uintptr_t dst = (uintptr_t)(a.out + base);
+            const uintptr_t a0 = dst & ~(uintptr_t)15;
+            const uint32_t lead = (uint32_t)(dst - a0);
+            const uint32_t nch = (lead + tot + 15) >> 4;
+            for (uint32_t c = tid; c < nch; c += kWG) {
+                const int32_t p0 = (int32_t)(c * 16) - (int32_t)lead;  // tile position of the chunk's byte 0
+                const uint32_t plo = (uint32_t)max(p0, 0);
+                uint32_t l = 0, h = nl;
+                while (h - l > 1) {
+                    const uint32_t mid = (l + h) >> 1;
+                    if (e[mid] <= plo) l = mid;
+                    else h = mid;
+                }
+                uint32_t q = l, qe = e[q + 1];
+                uint32_t wv[4] = {0, 0, 0, 0};
+#pragma unroll
+                for (int k = 0; k < 16; k++) {
+                    const int32_t p = p0 + k;
+                    if (p >= 0 && p < (int32_t)tot) {
+                        while ((uint32_t)p >= qe) {
+                            q++;
+                            qe = e[q + 1];
+                        }
+                        wv[k >> 2] |= (uint32_t)a.staging[src[q] + ((uint32_t)p - e[q])] << (8 * (k & 3));
+                    }
+                }
+                uint8_t* d = (uint8_t*)(a0 + ((uintptr_t)c << 4));
+                if (p0 >= 0 && p0 + 16 <= (int32_t)tot) {
+                    *(uint4*)d = make_uint4(wv[0], wv[1], wv[2], wv[3]);
+                } else {
+#pragma unroll
+                    for (int k = 0; k < 16; k++) {
+                        const int32_t p = p0 + k;
+                        if (p >= 0 && p < (int32_t)tot) d[k] = (uint8_t)(wv[k >> 2] >> (8 * (k & 3)));
+                    }
+                }
+            }
+        }
+        __syncthreads();
+    }
+    finish_workgroup(a.ws, a.res, gridDim.x, a.done);
+}
+
+// Zero the headers and the plan's counters; the plan's bins from the host's
+// configuration.
+struct BinInit {
+    uint32_t nbins;
+    uint32_t upper[kMaxBins];
+    uint32_t lpt[kMaxBins];
+};
+__global__ void binned_init_kernel(WsHeader* h1, WsHeader* h2, BinPlan* plan, BinInit cfg, ResultOut* res) {
+    const uint32_t i = threadIdx.x;
+    if (i == 0) {
+        WsHeader* hs[2] = {h1, h2};
+        for (int j = 0; j < 2; j++) {
+            hs[j]->ticket = 0;
+            hs[j]->done = 0;
+            hs[j]->enospc = 0;
+            hs[j]->errkey = ~0ull;
+            hs[j]->total = 0;
+        }
+        plan->nbins = cfg.nbins;
+        if (res) {
+            res->code = 0;
+            res->reserved = 0;
+            res->first_bad = -1;
+        }
+    }
+    if (i < kMaxBins) {
+        plan->upper[i] = cfg.upper[i];
+        plan->lpt[i] = cfg.lpt[i];
+        plan->ticket[i] = 0;
+    }
+}
+
+// ============================================================================
 // Line index
 // ============================================================================
 
@@ -1627,7 +2014,7 @@ size_t ws_bytes_for(int op, uint64_t n) {
             uint32_t nt = tiles_for(n, kCL);
             size_t st = ((size_t)nt * 8 + 255) & ~(size_t)255;
             size_t grid = (size_t)cus * kCompressWgPerCu;
-            return h + st + grid * kWG * kGenLane + grid * kSlotBytes;
+            return h + st + grid * kWG * kGenLane + grid * kCapSmall;
         }
         case ZS_OP_DECOMPRESS:
         case ZS_OP_DECOMPRESS_LINES: {
@@ -1641,6 +2028,56 @@ size_t ws_bytes_for(int op, uint64_t n) {
         default:
             return 0;
     }
+}
+
+
+// Workspace of the binned compression, carved in this order.
+struct BinnedWs {
+    WsHeader* h1;      // errors, ENOSPC (all launches)
+    WsHeader* h2;      // the placement pass's finishing count
+    BinPlan* plan;
+    uint32_t* hist;    // [chunk][kMaxBins]
+    uint64_t* status;  // look-back words of the compression tiles
+    uint8_t* gen;
+    uint8_t* slots;
+    uint32_t* ids;
+    uint32_t* pos_of;
+    uint64_t* soff;    // staging offsets in bin order, n + 1
+    uint32_t* ptotal;  // placement tile totals
+    uint64_t* pbase;   // their exclusive prefix, + 1
+    uint8_t* staging;
+    size_t bytes;
+    uint32_t max_tiles, nchunks, ptiles;
+};
+
+BinnedWs binned_ws(void* ws, uint64_t n, uint64_t out_cap, int cus) {
+    BinnedWs w;
+    uint8_t* b = (uint8_t*)ws;
+    size_t o = 0;
+    auto take = [&](size_t bytes) {
+        uint8_t* p = b ? b + o : nullptr;
+        o += align256(bytes);
+        return p;
+    };
+    w.max_tiles = (uint32_t)(n / 32 + kMaxBins + 1);  // tiles hold at least 32 lines, but the last of a bin
+    w.nchunks = tiles_for(n, kBinChunk);
+    w.ptiles = tiles_for(n, kCL);
+    const size_t grid = (size_t)cus * kCompressWgPerCu;
+    w.h1 = (WsHeader*)take(sizeof(WsHeader));
+    w.h2 = (WsHeader*)take(sizeof(WsHeader));
+    w.plan = (BinPlan*)take(sizeof(BinPlan));
+    w.hist = (uint32_t*)take((size_t)w.nchunks * kMaxBins * 4);
+    w.status = (uint64_t*)take((size_t)w.max_tiles * 8);
+    w.gen = take(grid * kWG * kGenLane);
+    w.slots = take(grid * kCapLarge);
+    w.ids = (uint32_t*)take(n * 4);
+    w.pos_of = (uint32_t*)take(n * 4);
+    w.soff = (uint64_t*)take((n + 1) * 8);
+    w.ptotal = (uint32_t*)take((size_t)w.ptiles * 4);
+    w.pbase = (uint64_t*)take(((size_t)w.ptiles + 1) * 8);
+    w.staging = take(out_cap + 16);
+    w.bytes = o;
+    return w;
 }
 
 }  // namespace
@@ -1693,11 +2130,16 @@ zs_status zs_dict_create(const uint8_t* len, const uint8_t* exp, zs_dict** out) 
         delete d;
         return ZS_EDEVICE;
     }
-    CompressLds cl = compress_lds(d->comp_bytes);
-    if (hipFuncSetAttribute((const void*)compress_kernel<8>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                            (int)cl.total) != hipSuccess ||
-        hipFuncSetAttribute((const void*)compress_kernel<16>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                            (int)cl.total) != hipSuccess ||
+    const int ls = (int)compress_lds(d->comp_bytes, kCapSmall).total;
+    const int ll = (int)compress_lds(d->comp_bytes, kCapLarge).total;
+    if (hipFuncSetAttribute((const void*)compress_kernel<8, kCapSmall>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                            ls) != hipSuccess ||
+        hipFuncSetAttribute((const void*)compress_kernel<16, kCapSmall>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                            ls) != hipSuccess ||
+        hipFuncSetAttribute((const void*)compress_kernel<8, kCapLarge>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                            ll) != hipSuccess ||
+        hipFuncSetAttribute((const void*)compress_kernel<16, kCapLarge>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                            ll) != hipSuccess ||
         hipFuncSetAttribute((const void*)decompress_kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
                             (int)decompress_lds().total) != hipSuccess) {
         (void)hipFree(d->d_tables);
@@ -1734,6 +2176,26 @@ static zs_status launch_init(WsHeader* h, uint64_t* status, uint32_t ntiles, Res
     if (blocks > 1024) blocks = 1024;
     hipLaunchKernelGGL(init_kernel, dim3(blocks), dim3(256), 0, s, h, status, ntiles, res);
     return hipGetLastError() == hipSuccess ? ZS_OK : ZS_EDEVICE;
+}
+
+// One compression launch: the persistent grid of the LDS variant, at most
+// max_tiles workgroups.
+static zs_status launch_compress(const zs_dict* d, const CompressArgs& a, bool large, uint32_t max_tiles, int cus,
+                                 hipStream_t s) {
+    const uint32_t lds = compress_lds(d->comp_bytes, large ? kCapLarge : kCapSmall).total;
+    const void* kfn = large ? (d->lk == 8 ? (const void*)compress_kernel<8, kCapLarge>
+                                          : (const void*)compress_kernel<16, kCapLarge>)
+                            : (d->lk == 8 ? (const void*)compress_kernel<8, kCapSmall>
+                                          : (const void*)compress_kernel<16, kCapSmall>);
+    int occ = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, kfn, kWG, lds) != hipSuccess || occ < 1) occ = 1;
+    if (occ > kCompressWgPerCu) occ = kCompressWgPerCu;
+    uint32_t grid = (uint32_t)cus * (uint32_t)occ;
+    if (grid > max_tiles) grid = max_tiles;
+    if (grid < 1) grid = 1;
+    void* args[] = {(void*)&a};
+    if (hipLaunchKernel(kfn, dim3(grid), dim3(kWG), args, lds, s) != hipSuccess) return ZS_EDEVICE;
+    return ZS_OK;
 }
 
 zs_status zs_compress(const zs_dict* d, const uint8_t* in, uint64_t in_bytes, const uint64_t* in_off,
@@ -1773,18 +2235,283 @@ zs_status zs_compress(const zs_dict* d, const uint8_t* in, uint64_t in_bytes, co
     a.gen = gen;
     a.slots = slots;
     a.res = (ResultOut*)res;
-    CompressLds cl = compress_lds(d->comp_bytes);
-    int occ = 0;
-    const void* kfn = d->lk == 8 ? (const void*)compress_kernel<8> : (const void*)compress_kernel<16>;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, kfn, kWG, cl.total) != hipSuccess || occ < 1) occ = 1;
-    if (occ > kCompressWgPerCu) occ = kCompressWgPerCu;
-    uint32_t grid = (uint32_t)di.cus * (uint32_t)occ;
-    if (grid > ntiles) grid = ntiles;
-    if (d->lk == 8)
-        hipLaunchKernelGGL(compress_kernel<8>, dim3(grid), dim3(kWG), cl.total, s, a);
-    else
-        hipLaunchKernelGGL(compress_kernel<16>, dim3(grid), dim3(kWG), cl.total, s, a);
+    a.ids = nullptr;
+    a.plan = nullptr;
+    a.bin_lo = a.bin_hi = 0;
+    a.ticket = nullptr;
+    return launch_compress(d, a, false, ntiles, di.cus, s);
+}
+
+
+size_t zs_binned_workspace_bytes(uint64_t n_lines, uint64_t out_cap) {
+    DeviceInfo di = device_info();
+    return binned_ws(nullptr, n_lines, out_cap, di.ok ? di.cus : 256).bytes;
+}
+
+zs_status zs_compress_binned(const zs_dict* d, const uint8_t* in, uint64_t in_bytes, const uint64_t* in_off,
+                             uint64_t n_lines, uint8_t* out, uint64_t out_cap, uint64_t* out_off, uint32_t flags,
+                             const zs_bin_config* cfg, void* ws, size_t ws_bytes, zs_result* res, void* stream) {
+    if (!d || !in_off || !out_off || !ws || !cfg || (!in && in_bytes)) return ZS_EINVAL;
+    if (flags & ~ZS_F_PREPROCESS) return ZS_EINVAL;
+    if (n_lines >= (1ull << 32)) return ZS_EINVAL;
+    const uint32_t nb = cfg->nbins;
+    if (nb < 1 || nb > kMaxBins) return ZS_EINVAL;
+    for (uint32_t i = 0; i + 1 < nb; i++)
+        if (cfg->edges[i] == 0 || (i > 0 && cfg->edges[i] <= cfg->edges[i - 1])) return ZS_EINVAL;
+    for (uint32_t i = 0; i < nb; i++)
+        if (cfg->lines_per_tile[i] < 1 || cfg->lines_per_tile[i] > (uint32_t)kCL || cfg->large_lds[i] > 1)
+            return ZS_EINVAL;
+    DeviceInfo di = device_info();
+    if (!di.ok) return ZS_EDEVICE;
+    const uint64_t cap = out ? out_cap : 0;
+    BinnedWs w = binned_ws(ws, n_lines, cap, di.cus);
+    if (ws_bytes < w.bytes) return ZS_EINVAL;
+    hipStream_t s = (hipStream_t)stream;
+    if (n_lines == 0) {
+        hipLaunchKernelGGL(empty_result_kernel, dim3(1), dim3(1), 0, s, out_off, (ResultOut*)res);
+        return hipGetLastError() == hipSuccess ? ZS_OK : ZS_EDEVICE;
+    }
+    // processing order: longest bin first
+    BinInit bi;
+    memset(&bi, 0, sizeof bi);
+    bi.nbins = nb;
+    uint32_t large[kMaxBins] = {0};
+    for (uint32_t b = 0; b < nb; b++) {
+        const uint32_t i = nb - 1 - b;  // the configuration's bin
+        bi.upper[b] = (i == nb - 1) ? 0xFFFFFFFFu : cfg->edges[i];
+        bi.lpt[b] = cfg->lines_per_tile[i];
+        large[b] = cfg->large_lds[i];
+    }
+    hipLaunchKernelGGL(binned_init_kernel, dim3(1), dim3(64), 0, s, w.h1, w.h2, w.plan, bi, (ResultOut*)res);
+    BinArgs ba;
+    ba.in_off = in_off;
+    ba.n = n_lines;
+    ba.in_bytes = in_bytes;
+    ba.plan = w.plan;
+    ba.hist = w.hist;
+    ba.nchunks = w.nchunks;
+    ba.ids = w.ids;
+    ba.pos_of = w.pos_of;
+    const uint32_t bgrid = std::min(w.nchunks, (uint32_t)di.cus * 8);
+    hipLaunchKernelGGL(bin_count_kernel, dim3(bgrid), dim3(kWG), 0, s, ba);
+    hipLaunchKernelGGL(bin_plan_kernel, dim3(1), dim3(kWG), 0, s, ba);
+    hipLaunchKernelGGL(bin_scatter_kernel, dim3(bgrid), dim3(kWG), 0, s, ba);
+    // zero the look-back words of every possible tile
+    hipLaunchKernelGGL(init_kernel, dim3(std::min(w.max_tiles / 256 + 1, 1024u)), dim3(256), 0, s, w.h2, w.status,
+                       w.max_tiles, (ResultOut*)nullptr);
+    if (hipGetLastError() != hipSuccess) return ZS_EDEVICE;
+    // one compression launch per run of bins that share an LDS layout
+    CompressArgs a;
+    a.tables = d->d_tables;
+    a.tab_bytes = d->comp_bytes;
+    a.in = in;
+    a.in_bytes = in_bytes;
+    a.in_off = in_off;
+    a.n = n_lines;
+    a.out = out ? w.staging : nullptr;
+    a.out_cap = out ? out_cap : ~0ull;
+    a.out_off = w.soff;
+    a.flags = flags;
+    a.ntiles = 0;
+    a.ws = w.h1;
+    a.status = w.status;
+    a.gen = w.gen;
+    a.slots = w.slots;
+    a.res = nullptr;
+    a.ids = w.ids;
+    a.plan = w.plan;
+    uint32_t b = 0, launch = 0;
+    while (b < nb) {
+        uint32_t e = b + 1;
+        while (e < nb && large[e] == large[b]) e++;
+        a.bin_lo = b;
+        a.bin_hi = e;
+        a.ticket = (uint32_t*)((uint8_t*)w.plan + offsetof(BinPlan, ticket)) + launch;
+        // an upper bound of this launch's tiles sizes the grid
+        uint64_t most = 0;
+        for (uint32_t k = b; k < e; k++) most += (n_lines + bi.lpt[k] - 1) / bi.lpt[k];
+        if (launch_compress(d, a, large[b] != 0, (uint32_t)std::min<uint64_t>(most, w.max_tiles), di.cus, s) != ZS_OK)
+            return ZS_EDEVICE;
+        b = e;
+        launch++;
+    }
+    // back to input order
+    PlaceArgs pa;
+    pa.pos_of = w.pos_of;
+    pa.soff = w.soff;
+    pa.staging = w.staging;
+    pa.n = n_lines;
+    pa.out = out;
+    pa.out_cap = out ? out_cap : ~0ull;
+    pa.out_off = out_off;
+    pa.ntiles = w.ptiles;
+    pa.tile_total = w.ptotal;
+    pa.tile_base = w.pbase;
+    pa.ws = w.h1;
+    pa.done = w.h2;
+    pa.res = (ResultOut*)res;
+    const uint32_t pgrid = std::min(w.ptiles, (uint32_t)di.cus * 8);
+    hipLaunchKernelGGL(place_count_kernel, dim3(pgrid), dim3(kWG), 0, s, pa);
+    hipLaunchKernelGGL(tile_scan_kernel, dim3(1), dim3(kScanWG), 0, s, w.ptotal, w.pbase, w.ptiles);
+    hipLaunchKernelGGL(place_write_kernel, dim3(pgrid), dim3(kWG), 0, s, pa);
     return hipGetLastError() == hipSuccess ? ZS_OK : ZS_EDEVICE;
+}
+
+
+zs_status zs_autotune_binned(const zs_dict* d, const uint8_t* in, uint64_t in_bytes, const uint64_t* in_off,
+                             uint64_t n_lines, uint32_t flags, zs_bin_config* best, double* best_ms,
+                             double* plain_ms, uint32_t* n_tried, void* stream) {
+    if (!d || !in_off || !best || n_lines == 0 || (!in && in_bytes)) return ZS_EINVAL;
+    hipStream_t s = (hipStream_t)stream;
+    // line lengths on the host: their quantiles give the candidate edges
+    std::vector<uint64_t> off(n_lines + 1);
+    if (hipMemcpyAsync(off.data(), in_off, off.size() * 8, hipMemcpyDeviceToHost, s) != hipSuccess ||
+        hipStreamSynchronize(s) != hipSuccess)
+        return ZS_EDEVICE;
+    std::vector<uint32_t> len(n_lines);
+    for (uint64_t k = 0; k < n_lines; k++)
+        len[k] = (uint32_t)std::min<uint64_t>(off[k + 1] > off[k] ? off[k + 1] - off[k] - 1 : 0, 1u << 20);
+    std::sort(len.begin(), len.end());
+    auto q = [&](double f) {
+        uint32_t v = len[std::min<uint64_t>(n_lines - 1, (uint64_t)(f * (double)n_lines))];
+        return std::max(8u, (v + 7) & ~7u);
+    };
+    const uint32_t lmax = len.back();
+    // buffers for the trials (exact output size from a size-only pass)
+    uint8_t *out = nullptr, *ws = nullptr, *wsb = nullptr;
+    uint64_t* oo = nullptr;
+    zs_result* res = nullptr;
+    zs_status rc = ZS_OK;
+    const size_t wsp = zs_workspace_bytes(ZS_OP_COMPRESS, n_lines);
+    if (hipMalloc(&oo, (n_lines + 1) * 8) != hipSuccess || hipMalloc(&ws, wsp) != hipSuccess ||
+        hipMalloc(&res, sizeof(zs_result)) != hipSuccess) {
+        rc = ZS_ENOMEM;
+    }
+    uint64_t total = 0;
+    if (rc == ZS_OK) rc = zs_compress(d, in, in_bytes, in_off, n_lines, nullptr, 0, oo, flags, ws, wsp, res, s);
+    if (rc == ZS_OK && (hipMemcpyAsync(&total, oo + n_lines, 8, hipMemcpyDeviceToHost, s) != hipSuccess ||
+                        hipStreamSynchronize(s) != hipSuccess))
+        rc = ZS_EDEVICE;
+    const size_t wsbytes = zs_binned_workspace_bytes(n_lines, total);
+    if (rc == ZS_OK && (hipMalloc(&out, total + 16) != hipSuccess || hipMalloc(&wsb, wsbytes) != hipSuccess))
+        rc = ZS_ENOMEM;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    if (rc == ZS_OK && (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess)) rc = ZS_EDEVICE;
+    // time one configuration (null: plain zs_compress): one warm-up, best of 3
+    auto run = [&](const zs_bin_config* c, double* ms) -> zs_status {
+        double bestt = 1e30;
+        for (int r = 0; r < 4; r++) {
+            if (hipEventRecord(e0, s) != hipSuccess) return ZS_EDEVICE;
+            zs_status z = c ? zs_compress_binned(d, in, in_bytes, in_off, n_lines, out, total + 16, oo, flags, c, wsb,
+                                                 wsbytes, res, s)
+                            : zs_compress(d, in, in_bytes, in_off, n_lines, out, total + 16, oo, flags, ws, wsp, res, s);
+            if (z != ZS_OK) return z;
+            if (hipEventRecord(e1, s) != hipSuccess || hipEventSynchronize(e1) != hipSuccess) return ZS_EDEVICE;
+            float t = 0;
+            if (hipEventElapsedTime(&t, e0, e1) != hipSuccess) return ZS_EDEVICE;
+            if (r > 0) bestt = std::min(bestt, (double)t);
+        }
+        *ms = bestt;
+        return ZS_OK;
+    };
+    double tplain = 0;
+    if (rc == ZS_OK) rc = run(nullptr, &tplain);
+    // candidates: edge sets x lines per tile of the longest bin x its LDS layout
+    std::vector<std::vector<uint32_t>> edge_sets = {{},
+                                                    {q(0.90)},
+                                                    {q(0.75)},
+                                                    {q(0.95)},
+                                                    {128},
+                                                    {192},
+                                                    {256},
+                                                    {q(0.50), q(0.90)},
+                                                    {q(0.75), q(0.95)},
+                                                    {128, 512},
+                                                    {q(0.90), 512}};
+    double tbest = 1e30;
+    zs_bin_config cbest;
+    memset(&cbest, 0, sizeof cbest);
+    uint32_t tried = 0;
+    for (auto& es : edge_sets) {
+        std::vector<uint32_t> e;
+        for (uint32_t v : es)
+            if (v < lmax && (e.empty() || v > e.back())) e.push_back(v);
+        if (e.size() != es.size() && !es.empty()) continue;  // a degenerate set repeats a smaller one
+        const uint32_t nb = (uint32_t)e.size() + 1;
+        for (uint32_t lpt : {256u, 128u, 64u}) {
+            for (uint32_t lg : {0u, 1u}) {
+                if (nb == 1 && lpt != 256) continue;
+                zs_bin_config c;
+                memset(&c, 0, sizeof c);
+                c.nbins = nb;
+                for (uint32_t i = 0; i + 1 < nb; i++) c.edges[i] = e[i];
+                for (uint32_t i = 0; i < nb; i++) c.lines_per_tile[i] = 256;
+                c.lines_per_tile[nb - 1] = lpt;
+                c.large_lds[nb - 1] = lg;
+                double t = 0;
+                if (rc == ZS_OK) rc = run(&c, &t);
+                if (rc != ZS_OK) break;
+                tried++;
+                if (t < tbest) {
+                    tbest = t;
+                    cbest = c;
+                }
+            }
+        }
+    }
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
+    if (out) (void)hipFree(out);
+    if (ws) (void)hipFree(ws);
+    if (wsb) (void)hipFree(wsb);
+    if (oo) (void)hipFree(oo);
+    if (res) (void)hipFree(res);
+    if (rc != ZS_OK) return rc;
+    *best = cbest;
+    if (best_ms) *best_ms = tbest;
+    if (plain_ms) *plain_ms = tplain;
+    if (n_tried) *n_tried = tried;
+    return ZS_OK;
+}
+
+struct zs_graph {
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+};
+
+zs_status zs_graph_begin(void* stream) {
+    if (!stream) return ZS_EINVAL;
+    return hipStreamBeginCapture((hipStream_t)stream, hipStreamCaptureModeThreadLocal) == hipSuccess ? ZS_OK
+                                                                                                    : ZS_EDEVICE;
+}
+
+zs_status zs_graph_end(void* stream, zs_graph** out) {
+    if (!stream || !out) return ZS_EINVAL;
+    zs_graph* g = new (std::nothrow) zs_graph;
+    if (!g) return ZS_ENOMEM;
+    if (hipStreamEndCapture((hipStream_t)stream, &g->graph) != hipSuccess || !g->graph) {
+        delete g;
+        return ZS_EDEVICE;
+    }
+    if (hipGraphInstantiate(&g->exec, g->graph, nullptr, nullptr, 0) != hipSuccess) {
+        (void)hipGraphDestroy(g->graph);
+        delete g;
+        return ZS_EDEVICE;
+    }
+    *out = g;
+    return ZS_OK;
+}
+
+zs_status zs_graph_launch(zs_graph* g, void* stream) {
+    if (!g) return ZS_EINVAL;
+    return hipGraphLaunch(g->exec, (hipStream_t)stream) == hipSuccess ? ZS_OK : ZS_EDEVICE;
+}
+
+void zs_graph_destroy(zs_graph* g) {
+    if (!g) return;
+    if (g->exec) (void)hipGraphExecDestroy(g->exec);
+    if (g->graph) (void)hipGraphDestroy(g->graph);
+    delete g;
 }
 
 static zs_status decompress_common(const zs_dict* d, const uint8_t* in, uint64_t in_bytes, const uint64_t* in_off,

@@ -202,3 +202,29 @@ def test_kernel_recurrence_matches_oracle():
             s = bytes(rnd.choice(alphabet) for _ in range(rnd.randint(0, 25)))
             got, _ = t2.parse(s)
             assert got == oracle.compress_line(od2, s, preprocess=False), (ents, s)
+
+
+def test_binned_config_validation():
+    """zs_compress_binned rejects bad bin configurations on the host, before any device work."""
+    import ctypes
+    import paper_2404_19391_amd as zs
+    L = zs.lib()
+    fake = ctypes.c_void_p(16)
+
+    def call(cfg, flags=1, n=10):
+        return L.zs_compress_binned(fake, fake, 100, fake, n, fake, 100, fake, flags, ctypes.byref(cfg), fake,
+                                    1 << 40, fake, None)
+
+    bad = [zs.BinConfig.make(edges=(128, 128)), zs.BinConfig.make(edges=(256, 128)),
+           zs.BinConfig.make(edges=(0,)), zs.BinConfig.make(lines_per_tile=(0,)),
+           zs.BinConfig.make(lines_per_tile=(257,)), zs.BinConfig.make(large_lds=(2,))]
+    for c in bad:
+        assert call(c) == zs.EINVAL
+    c = zs.BinConfig.make()
+    c.nbins = 0
+    assert call(c) == zs.EINVAL
+    c.nbins = zs.MAX_BINS + 1
+    assert call(c) == zs.EINVAL
+    assert call(zs.BinConfig.make(), flags=4) == zs.EINVAL
+    assert call(zs.BinConfig.make(), n=1 << 32) == zs.EINVAL
+    assert L.zs_graph_begin(None) == zs.EINVAL
