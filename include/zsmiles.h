@@ -166,7 +166,7 @@ typedef struct {
     uint32_t nbins;                        /* 1..ZS_MAX_BINS                                      */
     uint32_t edges[ZS_MAX_BINS - 1];       /* ascending raw-length bounds: bin i holds lengths in */
                                            /* [edges[i-1], edges[i]) (edges[-1] = 0, last open)   */
-    uint32_t lines_per_tile[ZS_MAX_BINS];  /* per bin, 1..256: lines (lanes) per workgroup tile   */
+    uint32_t lines_per_tile[ZS_MAX_BINS];  /* per bin, 32..256: lines (lanes) per workgroup tile  */
     uint32_t large_lds[ZS_MAX_BINS];       /* per bin, 0 or 1: the LDS layout with the larger     */
                                            /* line batch (2 workgroups per CU instead of 3)       */
 } zs_bin_config;

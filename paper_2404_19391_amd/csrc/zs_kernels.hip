@@ -50,7 +50,7 @@ constexpr int kCL = 256;              // lines per tile at most (one per thread)
 // large one (long lines) 2.
 constexpr int kCapSmall = 14336;
 constexpr int kCapLarge = 26624;
-constexpr int kSlots = 8;             // fast ring tables (registers): open rings, slot = label % 8
+constexpr int kSlots = 16;            // fast ring table (registers): up to 16 open rings, found by label
 constexpr int kGenLane = 400;         // per-lane ring tables in global memory (any line):
                                       // 100 open positions u16 + 100 last-close u16
 static_assert(kCapSmall >= 3 * (int)ZS_MAX_LINE, "a pre-processed line must fit");
@@ -313,12 +313,12 @@ struct Compressor {
         *has_pct = pct_any != 0;
     }
 
-    // Ring IDs from the label list with register tables: kSlots open rings
-    // (slot = label % kSlots) and, per open ring, the bit set of the IDs of the
-    // rings that closed inside it; a closing ring takes the smallest ID not in
-    // its set (Sec. IV-A).  Markers are written over the raw line.  Sets
-    // *overflow when a slot collides or an ID reaches 32; returns false when
-    // rings stay open.
+    // Ring IDs from the label list with a register table of kSlots open rings
+    // (found by label value, free slots reused) and, per open ring, the bit set
+    // of the IDs of the rings that closed inside it; a closing ring takes the
+    // smallest ID not in its set (Sec. IV-A).  Markers are written over the
+    // raw line.  Sets *overflow when more than kSlots rings are open at once or
+    // an ID reaches 32; returns false when rings stay open.
     __device__ __forceinline__ bool ring_fast(uint8_t* raw, uint32_t R, const uint16_t* list, uint32_t nlab, uint32_t maxlab,
                               int* delta, bool* overflow, bool* marked) {
         bool mk_any = false;
@@ -339,14 +339,26 @@ struct Compressor {
                     v = c0 - '0';
                     tl = 1;
                 }
-                const uint32_t slot = v & (kSlots - 1);
-                uint32_t e = 0, m = 0;
+                // the open ring of label v, else the first free slot
+                uint32_t slot = kSlots, freeslot = kSlots;
 #pragma unroll
-                for (int k = 0; k < kSlots; k++) {
-                    e = (slot == (uint32_t)k) ? os[k] : e;
-                    m = (slot == (uint32_t)k) ? mk[k] : m;
+                for (int k = kSlots - 1; k >= 0; k--) {
+                    slot = (os[k] != 0 && (os[k] & 0xFFu) == v) ? (uint32_t)k : slot;
+                    freeslot = (os[k] == 0) ? (uint32_t)k : freeslot;
                 }
-                if (e == 0) {
+                uint32_t e = 0, m = 0;
+                if (slot == kSlots) {
+                    slot = freeslot;
+                } else {
+#pragma unroll
+                    for (int k = 0; k < kSlots; k++) {
+                        e = (slot == (uint32_t)k) ? os[k] : e;
+                        m = (slot == (uint32_t)k) ? mk[k] : m;
+                    }
+                }
+                if (slot == kSlots) {
+                    ovf = true;  // more than kSlots rings open
+                } else if (e == 0) {
 #pragma unroll
                     for (int k = 0; k < kSlots; k++) {
                         os[k] = (slot == (uint32_t)k) ? (((p + 1) << 8) | v) : os[k];
@@ -378,8 +390,6 @@ struct Compressor {
                         mk_any |= (nlen != 1) | (to != 1) | (tl != 1);
                         dl += (nlen - (int)to) + (nlen - (int)tl);
                     }
-                } else {
-                    ovf = true;
                 }
             }
         }
@@ -1529,6 +1539,7 @@ __global__ void __launch_bounds__(kScanWG) tile_scan_kernel(const uint32_t* tota
 // ============================================================================
 
 constexpr int kBinChunk = 4096;  // lines per workgroup of the binning kernels
+constexpr uint32_t kMinLpt = 32;  // fewest lines per tile a bin may ask for (bounds the tile count)
 
 // Processing-order bin of a line of raw length len (bad framing: the last bin).
 __device__ inline uint32_t bin_of(const BinPlan* plan, uint64_t a, uint64_t b, uint64_t in_bytes) {
@@ -2059,7 +2070,8 @@ BinnedWs binned_ws(void* ws, uint64_t n, uint64_t out_cap, int cus) {
         o += align256(bytes);
         return p;
     };
-    w.max_tiles = (uint32_t)(n / 32 + kMaxBins + 1);  // tiles hold at least 32 lines, but the last of a bin
+    // every tile but the last of a bin holds at least kMinLpt lines
+    w.max_tiles = (uint32_t)(n / kMinLpt + kMaxBins + 1);
     w.nchunks = tiles_for(n, kBinChunk);
     w.ptiles = tiles_for(n, kCL);
     const size_t grid = (size_t)cus * kCompressWgPerCu;
@@ -2259,7 +2271,7 @@ zs_status zs_compress_binned(const zs_dict* d, const uint8_t* in, uint64_t in_by
     for (uint32_t i = 0; i + 1 < nb; i++)
         if (cfg->edges[i] == 0 || (i > 0 && cfg->edges[i] <= cfg->edges[i - 1])) return ZS_EINVAL;
     for (uint32_t i = 0; i < nb; i++)
-        if (cfg->lines_per_tile[i] < 1 || cfg->lines_per_tile[i] > (uint32_t)kCL || cfg->large_lds[i] > 1)
+        if (cfg->lines_per_tile[i] < kMinLpt || cfg->lines_per_tile[i] > (uint32_t)kCL || cfg->large_lds[i] > 1)
             return ZS_EINVAL;
     DeviceInfo di = device_info();
     if (!di.ok) return ZS_EDEVICE;
@@ -2438,7 +2450,7 @@ zs_status zs_autotune_binned(const zs_dict* d, const uint8_t* in, uint64_t in_by
             if (v < lmax && (e.empty() || v > e.back())) e.push_back(v);
         if (e.size() != es.size() && !es.empty()) continue;  // a degenerate set repeats a smaller one
         const uint32_t nb = (uint32_t)e.size() + 1;
-        for (uint32_t lpt : {256u, 128u, 64u}) {
+        for (uint32_t lpt : {256u, 128u, 64u, 32u}) {
             for (uint32_t lg : {0u, 1u}) {
                 if (nb == 1 && lpt != 256) continue;
                 zs_bin_config c;

@@ -16,7 +16,7 @@ CONFIGS = [
     dict(edges=()),
     dict(edges=(128,), lines_per_tile=(256, 64), large_lds=(0, 1)),
     dict(edges=(64, 256), lines_per_tile=(256, 128, 32), large_lds=(0, 0, 1)),
-    dict(edges=(16, 32, 48, 64, 96, 128, 400), lines_per_tile=(256, 200, 160, 128, 96, 64, 33, 7),
+    dict(edges=(16, 32, 48, 64, 96, 128, 400), lines_per_tile=(256, 200, 160, 128, 96, 64, 33, 32),
          large_lds=(1, 0, 1, 0, 1, 0, 1, 0)),
 ]
 
