@@ -43,6 +43,14 @@ def parse():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--cpu-lines", type=int, default=120_000)
     ap.add_argument("--only", default="", help="comma list of ops to run (profiling runs)")
+    ap.add_argument("--workload", default="bulk", choices=["bulk", "uneven", "serve"],
+                    help="bulk: the headline step; uneven: plain vs length-binned / autotuned / graph "
+                         "compression; serve: the request loop under Poisson arrivals")
+    ap.add_argument("--serve-requests", type=int, default=10000)
+    ap.add_argument("--serve-gb", type=float, default=50.0, help="compressed shard bytes resident (GB)")
+    ap.add_argument("--shard-lines", type=int, default=40_000_000)
+    ap.add_argument("--slots", type=int, default=16)
+    ap.add_argument("--tune-lines", type=int, default=1_000_000, help="sample the autotuner times (uneven)")
     return ap.parse_args()
 
 
@@ -88,6 +96,295 @@ def cpu_baseline(buf, off, n_sample):
     }
 
 
+def time_ms(fn, stream, reps):
+    """Per-call times (ms) of fn on stream, HIP events around each call."""
+    import torch
+    out = []
+    for _ in range(reps):
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        fn()
+        e1.record(stream)
+        e1.synchronize()
+        out.append(e0.elapsed_time(e1))
+    return out
+
+
+def bench_uneven(args):
+    """Uneven line lengths: 20M lines, 90% drug-like (10..120 chars) and 10% long chains
+    (200..1,000 chars, deep branches, %nn ring labels), drawn independently per line.
+    Compression by the plain call, by the length-binned call with a fixed configuration,
+    with the autotuned configuration, and as a replayed HIP graph of the autotuned call;
+    all four must give the same bytes."""
+    import torch
+    import paper_2404_19391_amd as zs
+    import smilesgen
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    n = args.lines if args.lines != 10_000_000 else 20_000_000
+    log("generating %d uneven lines" % n)
+    buf, off = smilesgen.generate("uneven", 3, n, threads=16)
+    raw = int(buf.size)
+    d = zs.Dict.load()
+    b = torch.from_numpy(buf).to(dev)
+    o = torch.from_numpy(off.astype(np.int64)).to(dev)
+    del buf
+    stream = torch.cuda.current_stream()
+    res = zs.new_result(dev)
+    oo = torch.empty(n + 1, dtype=torch.int64, device=dev)
+    ws_p = zs.Workspaces(dev).get(zs.OP_COMPRESS, n)
+    zs.compress_into(d, b, o, None, oo, ws_p, res)
+    total = int(oo[-1].item())
+    out_p = torch.empty(total, dtype=torch.uint8, device=dev)
+    zs.compress_into(d, b, o, out_p, oo, ws_p, res)
+    torch.cuda.synchronize()
+    ref_off = oo.clone()
+    log("plain: %d -> %d bytes" % (raw, total))
+    # autotune on a sample (the first tune-lines lines)
+    k = min(args.tune_lines, n)
+    t0 = time.perf_counter()
+    cfg_t, tuned_ms, plain_sample_ms, tried = zs.autotune_binned(d, b, o[:k + 1])
+    tune_s = time.perf_counter() - t0
+    log("autotuned on %d lines in %.1f s over %d configs: %s" % (k, tune_s, tried, cfg_t.as_dict()))
+    cfg_f = zs.BinConfig.make(edges=(128,), lines_per_tile=(256, 64), large_lds=(0, 1))
+    ws_b = torch.empty(zs.binned_workspace_bytes(n, total), dtype=torch.uint8, device=dev)
+    out_b = torch.empty(total, dtype=torch.uint8, device=dev)
+    ob = torch.empty(n + 1, dtype=torch.int64, device=dev)
+    runs = {
+        "plain": lambda: zs.compress_into(d, b, o, out_p, oo, ws_p, res),
+        "binned_fixed": lambda: zs.compress_binned_into(d, b, o, out_b, ob, cfg_f, ws_b, res),
+        "binned_autotuned": lambda: zs.compress_binned_into(d, b, o, out_b, ob, cfg_t, ws_b, res),
+    }
+    identical = {}
+    times = {}
+    for name, fn in runs.items():
+        for _ in range(args.warmup):
+            fn()
+        torch.cuda.synchronize()
+        times[name] = time_ms(fn, stream, args.steps)
+        code, fb = zs.read_result(res)
+        identical[name] = bool(code == 0 and torch.equal(out_b if name != "plain" else out_p, out_p)
+                               and torch.equal(ob if name != "plain" else oo, ref_off))
+    # the autotuned call as a HIP graph on a side stream
+    s = torch.cuda.Stream(device=dev)
+    g = zs.Graph()
+    out_b.fill_(0)
+    torch.cuda.synchronize()
+    with torch.cuda.stream(s):
+        with g.capture(s):
+            zs.compress_binned_into(d, b, o, out_b, ob, cfg_t, ws_b, res)
+    for _ in range(args.warmup):
+        g.replay(s)
+    s.synchronize()
+    times["binned_autotuned_graph"] = time_ms(lambda: g.replay(s), s, args.steps)
+    identical["binned_autotuned_graph"] = bool(torch.equal(out_b, out_p) and torch.equal(ob, ref_off))
+    med = {k: float(np.median(v)) for k, v in times.items()}
+    best = min(med, key=med.get)
+    per = {k: {"ms": round(v, 3), "user_GBs": round(raw / (v * 1e-3) / 1e9, 2),
+               "speedup_vs_plain": round(med["plain"] / v, 3), "identical_to_plain": identical[k]}
+           for k, v in med.items()}
+    alg = raw + 2 * 8 * (n + 1) + total
+    out = {
+        "metric": METRIC,
+        "value": round(raw / (med[best] * 1e-3) / 1e9, 3),
+        "unit": "GB/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(med[best], 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "u8",
+        "data": "synthetic",
+        "config": {"workload": "uneven: %d synthetic SMILES lines, 90%% log-normal 10..120 chars, 10%% long "
+                               "chains 200..1000 chars, %.3f GB raw, default dictionary; compression only"
+                               % (n, raw / 1e9),
+                   "lines": n, "raw_bytes": raw, "compressed_bytes": total, "best": best},
+        "roofline": {"kernel": "compress (%s)" % best, "bound": "hbm", "achieved": round(alg / (med[best] * 1e-3) / 1e9, 2),
+                     "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": round(alg / (med[best] * 1e-3) / 1e9 / HBM_PEAK_GBS, 4), "traffic": None},
+        "compress": per,
+        "autotune": {"sample_lines": k, "configs_timed": tried, "seconds": round(tune_s, 2),
+                     "chosen": cfg_t.as_dict(), "sample_best_ms": round(tuned_ms, 3),
+                     "sample_plain_ms": round(plain_sample_ms, 3)},
+        "fixed_config": cfg_f.as_dict(),
+    }
+    print(json.dumps(out), flush=True)
+
+
+def bench_serve(args):
+    """Request loop: replicas of one compressed shard (the shard's lines from the bulk
+    distribution) resident in HBM with their indexes and one dictionary; 70% random-access
+    requests of log-uniform 1..100,000 ids over (replica x line), 30% compression requests of
+    log-uniform 1..1,000,000 fresh lines (slices of a pool generated with another seed).
+    First the closed-loop capacity (2 x slots clients), then Poisson arrivals at 0.7 x that
+    rate; latency = completion - scheduled arrival."""
+    import threading
+    import torch
+    import paper_2404_19391_amd as zs
+    import smilesgen
+    import oracle
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    d = zs.Dict.load()
+    n = args.shard_lines
+    log("generating the %d-line shard" % n)
+    buf, off = smilesgen.generate("bulk", 4, n, threads=16)
+    b = torch.from_numpy(buf).to(dev)
+    o = torch.from_numpy(off.astype(np.int64)).to(dev)
+    del buf, off
+    c, co = zs.compress(d, b, o)
+    del b, o
+    torch.cuda.synchronize()
+    cbytes = int(c.numel())
+    reps = max(1, int(np.ceil(args.serve_gb * 1e9 / cbytes)))
+    log("shard: %d lines -> %.3f GB compressed; %d replicas resident" % (n, cbytes / 1e9, reps))
+    srv = zs.Server(d, slots=args.slots, device_bytes=24 << 30, host_bytes=16 << 30)
+    shards = [(c, co)] + [(c.clone(), co.clone()) for _ in range(reps - 1)]
+    sids = [srv.add_shard(x, y) for x, y in shards]
+    torch.cuda.synchronize()
+    resident = sum(int(x.numel()) + 8 * int(y.numel()) for x, y in shards)
+    log("pool of fresh lines")
+    pbuf, poff = smilesgen.generate("bulk", 56, 2_000_000, threads=16)
+    host_c = c.cpu().numpy()
+    host_co = co.cpu().numpy().astype(np.uint64)
+
+    def make(rng):
+        if rng.random() < 0.7:
+            k = int(np.exp(rng.uniform(0, np.log(100_000))))
+            return ("d", int(rng.integers(0, reps)), rng.integers(0, n, k).astype(np.uint64))
+        k = int(np.exp(rng.uniform(0, np.log(1_000_000))))
+        s0 = int(rng.integers(0, poff.size - 1 - k))
+        lines = pbuf[int(poff[s0]):int(poff[s0 + k])]
+        return ("c", s0, k, lines, (poff[s0:s0 + k + 1] - poff[s0]).astype(np.uint64))
+
+    def submit(r):
+        if r[0] == "d":
+            return srv.submit_decompress(sids[r[1]], r[2])
+        return srv.submit_compress(r[3], r[4])
+
+    def user_bytes(r, data):
+        return data.size if r[0] == "d" else r[3].size
+
+    # closed loop: capacity
+    ncl = max(2, 2 * args.slots)
+    per = max(20, args.serve_requests // (5 * ncl))
+    done_bytes = [0] * ncl
+
+    def client(i):
+        rng = np.random.default_rng(1000 + i)
+        for _ in range(per):
+            r = make(rng)
+            code, fb, data, offs, t = srv.wait(submit(r))
+            done_bytes[i] += user_bytes(r, data)
+
+    log("closed loop: %d clients x %d requests" % (ncl, per))
+    t0 = time.perf_counter()
+    th = [threading.Thread(target=client, args=(i,)) for i in range(ncl)]
+    for t in th:
+        t.start()
+    for t in th:
+        t.join()
+    cap_s = time.perf_counter() - t0
+    capacity = ncl * per / cap_s
+    # open loop: Poisson arrivals at 0.7 x capacity
+    rate = 0.7 * capacity
+    nreq = args.serve_requests
+    rng = np.random.default_rng(5)
+    gaps = rng.exponential(1.0 / rate, nreq)
+    rreq = np.random.default_rng(55)
+    reqs = [make(rreq) for _ in range(nreq)]
+    lat = np.zeros(nreq)
+    kinds = np.array([r[0] == "d" for r in reqs])
+    ubytes = np.zeros(nreq)
+    replies = {}
+    verify = set(int(x) for x in np.random.default_rng(7).choice(nreq, min(200, nreq), replace=False))
+    tickets = [None] * nreq
+    arrive = np.zeros(nreq)
+    ready = threading.Semaphore(0)
+
+    def waiter():
+        while True:
+            ready.acquire()
+            i = next_wait[0]
+            next_wait[0] += 1
+            if i >= nreq:
+                return
+            code, fb, data, offs, t = srv.wait(tickets[i])
+            lat[i] = t["done"] - arrive[i]
+            ubytes[i] = user_bytes(reqs[i], data)
+            if i in verify or code != 0:
+                replies[i] = (code, fb, data, offs)
+
+    next_wait = [0]
+    log("open loop: %d requests at %.1f req/s" % (nreq, rate))
+    wt = threading.Thread(target=waiter)
+    wt.start()
+    base = time.monotonic()
+    at = base
+    for i in range(nreq):
+        at += gaps[i]
+        now = time.monotonic()
+        if at > now:
+            time.sleep(at - now)
+        arrive[i] = at
+        tickets[i] = submit(reqs[i])
+        ready.release()
+    ready.release()
+    wt.join()
+    span = max(time.monotonic() - base, 1e-9)
+    st = srv.stats()
+    srv.close()
+    # verification of a sample against the oracle
+    od = oracle.Dict.load(zs.default_dict_path())
+    checked = bad = 0
+    for i in sorted(verify):
+        r = reqs[i]
+        code, fb, data, offs = replies[i]
+        if r[0] == "d":
+            w = oracle.decompress_lines(od, host_c, host_co, r[2])
+        else:
+            if r[2] > 20000:
+                continue
+            w = oracle.compress(od, r[3], r[4])
+        checked += 1
+        bad += not (code == w[0] and data.tobytes() == w[2].tobytes() and np.array_equal(offs, w[3]))
+    errors = sum(1 for i in replies if replies[i][0] != 0)
+    p = lambda a, q: round(float(np.percentile(a, q)) * 1e3, 3) if a.size else None
+    out = {
+        "metric": METRIC,
+        "value": round(float(ubytes.sum()) / span / 1e9, 3),
+        "unit": "GB/s",
+        "n_gpus": 1,
+        "steps": nreq,
+        "warmup": ncl * per,
+        "ms_per_step": round(span / nreq * 1e3, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "u8",
+        "data": "synthetic",
+        "config": {"workload": "serving: %d replicas of a %d-line compressed shard (%.1f GB compressed + %.1f GB "
+                               "indexes resident), 70%% random access of 1..100k ids, 30%% compression of 1..1M "
+                               "new lines, Poisson arrivals at 0.7 x closed-loop capacity"
+                               % (reps, n, reps * cbytes / 1e9, (resident - reps * cbytes) / 1e9),
+                   "slots": args.slots, "requests": nreq},
+        "serving": {"offered_req_s": round(rate, 2), "achieved_req_s": round(nreq / span, 2),
+                    "closed_loop_capacity_req_s": round(capacity, 2),
+                    "latency_ms": {"p50": p(lat, 50), "p99": p(lat, 99),
+                                   "random_access_p50": p(lat[kinds], 50), "random_access_p99": p(lat[kinds], 99),
+                                   "compress_p50": p(lat[~kinds], 50), "compress_p99": p(lat[~kinds], 99)},
+                    "user_GBs": round(float(ubytes.sum()) / span / 1e9, 3),
+                    "resident_GB": round(resident / 1e9, 2),
+                    "verified": {"checked": checked, "mismatches": bad, "sample": "random requests, compression "
+                                 "requests of at most 20,000 lines, against the oracle"},
+                    "error_replies": errors, "server": st},
+    }
+    print(json.dumps(out), flush=True)
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -101,6 +398,10 @@ def main():
     if not torch.cuda.is_available():
         print("no GPU visible", file=sys.stderr)
         sys.exit(1)
+    if args.workload == "uneven":
+        return bench_uneven(args)
+    if args.workload == "serve":
+        return bench_serve(args)
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
     only = set(args.only.split(",")) if args.only else {"index", "compress", "decompress", "random"}

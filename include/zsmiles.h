@@ -203,6 +203,58 @@ zs_status zs_graph_end(void *stream, zs_graph **out);
 zs_status zs_graph_launch(zs_graph *g, void *stream);
 void zs_graph_destroy(zs_graph *g);
 
+/*
+ * Request loop (one GPU).  Compressed shards stay resident in device memory
+ * (registered with zs_server_add_shard, owned by the caller) and share one
+ * dictionary; random-access decompression requests (ids of a shard) and
+ * compression requests (new lines) may be submitted from any host thread.  A
+ * scheduler thread admits them in arrival order into `slots` HIP streams, so
+ * the work of many requests overlaps on the device.  Admission is by device
+ * footprint: a request first runs its call in size-only mode, then takes an
+ * output buffer of the exact size from a device arena of `device_bytes`
+ * (made at creation: the loop itself allocates nothing).  Inputs are copied
+ * at submission into a pinned host arena of `host_bytes`; results come back
+ * there.  zs_server_wait blocks until a request is done and describes its
+ * result, which stays valid until zs_server_release.  Every result equals
+ * what the same call gives on its own.
+ */
+typedef struct zs_server zs_server;
+typedef struct {
+    uint32_t slots;         /* concurrent requests (streams), 1..64 */
+    uint64_t device_bytes;  /* device arena for request buffers     */
+    uint64_t host_bytes;    /* pinned host arena for inputs/outputs */
+} zs_server_config;
+typedef struct {
+    int32_t code;           /* zs_status of the data (as zs_result)        */
+    int64_t first_bad;
+    uint64_t n;             /* ids or lines                                 */
+    const uint64_t *off;    /* host: n+1 output offsets                     */
+    const uint8_t *data;    /* host: output bytes                           */
+    uint64_t bytes;
+    double t_submit, t_admit, t_done;  /* seconds, one steady clock         */
+    uint64_t footprint;     /* device bytes the request held                */
+} zs_reply;
+typedef struct {
+    uint64_t submitted, admitted, completed, deferred;
+    uint64_t peak_device_bytes, device_bytes_in_use;
+    double busy_s;          /* sum over requests of admit-to-done time      */
+} zs_server_stats;
+
+zs_status zs_server_create(const zs_dict *d, const zs_server_config *cfg, zs_server **out);
+zs_status zs_server_add_shard(zs_server *s, const uint8_t *in, uint64_t in_bytes, const uint64_t *in_off,
+                              uint64_t n_lines, uint32_t *shard);
+/* ids: host array, copied; ZS_ENOSPC if the request can never fit the arenas. */
+zs_status zs_server_submit_decompress(zs_server *s, uint32_t shard, const uint64_t *ids, uint64_t n_ids,
+                                      uint64_t *ticket);
+/* lines, off: host arrays (off[0..n], absolute in lines), copied. */
+zs_status zs_server_submit_compress(zs_server *s, const uint8_t *lines, uint64_t bytes, const uint64_t *off,
+                                    uint64_t n_lines, uint32_t flags, uint64_t *ticket);
+zs_status zs_server_wait(zs_server *s, uint64_t ticket, zs_reply *out);
+void zs_server_release(zs_server *s, uint64_t ticket);
+zs_status zs_server_get_stats(zs_server *s, zs_server_stats *out);
+/* Finishes the admitted and queued requests, then frees everything. */
+void zs_server_destroy(zs_server *s);
+
 /* Human-readable name of a status code. */
 const char *zs_status_str(int code);
 

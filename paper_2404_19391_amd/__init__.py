@@ -71,6 +71,26 @@ class BinConfig(ctypes.Structure):
                 "large_lds": [int(self.large_lds[i]) for i in range(n)]}
 
 
+class ServerConfig(ctypes.Structure):
+    _fields_ = [("slots", ctypes.c_uint32), ("device_bytes", ctypes.c_uint64), ("host_bytes", ctypes.c_uint64)]
+
+
+class Reply(ctypes.Structure):
+    _fields_ = [("code", ctypes.c_int32), ("first_bad", ctypes.c_int64), ("n", ctypes.c_uint64),
+                ("off", ctypes.POINTER(ctypes.c_uint64)), ("data", ctypes.POINTER(ctypes.c_uint8)),
+                ("bytes", ctypes.c_uint64), ("t_submit", ctypes.c_double), ("t_admit", ctypes.c_double),
+                ("t_done", ctypes.c_double), ("footprint", ctypes.c_uint64)]
+
+
+class ServerStats(ctypes.Structure):
+    _fields_ = [("submitted", ctypes.c_uint64), ("admitted", ctypes.c_uint64), ("completed", ctypes.c_uint64),
+                ("deferred", ctypes.c_uint64), ("peak_device_bytes", ctypes.c_uint64),
+                ("device_bytes_in_use", ctypes.c_uint64), ("busy_s", ctypes.c_double)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
 def lib():
     """The loaded libzsmiles.so; raises if it has not been built."""
     global _lib
@@ -119,6 +139,22 @@ def lib():
         L.zs_graph_launch.argtypes = [_vp, _vp]
         L.zs_graph_destroy.restype = None
         L.zs_graph_destroy.argtypes = [_vp]
+        L.zs_server_create.restype = ctypes.c_int
+        L.zs_server_create.argtypes = [_vp, ctypes.POINTER(ServerConfig), ctypes.POINTER(_vp)]
+        L.zs_server_add_shard.restype = ctypes.c_int
+        L.zs_server_add_shard.argtypes = [_vp, _vp, _u64, _vp, _u64, ctypes.POINTER(ctypes.c_uint32)]
+        L.zs_server_submit_decompress.restype = ctypes.c_int
+        L.zs_server_submit_decompress.argtypes = [_vp, ctypes.c_uint32, _vp, _u64, ctypes.POINTER(_u64)]
+        L.zs_server_submit_compress.restype = ctypes.c_int
+        L.zs_server_submit_compress.argtypes = [_vp, _vp, _u64, _vp, _u64, ctypes.c_uint32, ctypes.POINTER(_u64)]
+        L.zs_server_wait.restype = ctypes.c_int
+        L.zs_server_wait.argtypes = [_vp, _u64, ctypes.POINTER(Reply)]
+        L.zs_server_release.restype = None
+        L.zs_server_release.argtypes = [_vp, _u64]
+        L.zs_server_get_stats.restype = ctypes.c_int
+        L.zs_server_get_stats.argtypes = [_vp, ctypes.POINTER(ServerStats)]
+        L.zs_server_destroy.restype = None
+        L.zs_server_destroy.argtypes = [_vp]
         L.zsi_compile_dict_c.restype = ctypes.c_int
         L.zsi_compile_dict_c.argtypes = [_vp, _vp, _vp, _u64, ctypes.POINTER(_u64)]
         _lib = L
@@ -451,3 +487,73 @@ def index_lines(buf, check=True):
     index_into(buf, off, n_out, ws, res)
     _check_res(res, "index_lines", check)
     return off
+
+
+# ---- request loop ----------------------------------------------------------------------------------
+
+class Server:
+    """zs_server: resident shards, requests from any thread, admission by exact device footprint.
+
+    submit_* return a ticket; wait(ticket) returns (code, first_bad, data uint8 array, offsets uint64
+    array, timings dict) and releases the request's host buffers."""
+
+    def __init__(self, d, slots=8, device_bytes=4 << 30, host_bytes=2 << 30):
+        self.d = d
+        cfg = ServerConfig(slots, device_bytes, host_bytes)
+        h = _vp()
+        _check_rc(lib().zs_server_create(d.handle, ctypes.byref(cfg), ctypes.byref(h)), "zs_server_create")
+        self.handle = h
+        self._keep = []
+
+    def add_shard(self, buf, off):
+        """Register a device-resident compressed shard (uint8 bytes, int64 offsets); returns its id."""
+        sid = ctypes.c_uint32(0)
+        _check_rc(lib().zs_server_add_shard(self.handle, _p(buf), buf.numel(), _p(off), off.numel() - 1,
+                                            ctypes.byref(sid)), "zs_server_add_shard")
+        self._keep.append((buf, off))
+        return int(sid.value)
+
+    def submit_decompress(self, shard, ids):
+        ids = np.ascontiguousarray(ids, dtype=np.uint64)
+        t = _u64(0)
+        _check_rc(lib().zs_server_submit_decompress(self.handle, shard, ids.ctypes.data_as(_vp), ids.size,
+                                                    ctypes.byref(t)), "zs_server_submit_decompress")
+        return int(t.value)
+
+    def submit_compress(self, lines, off, preprocess=True):
+        lines = np.ascontiguousarray(lines, dtype=np.uint8)
+        off = np.ascontiguousarray(off, dtype=np.uint64)
+        t = _u64(0)
+        _check_rc(lib().zs_server_submit_compress(self.handle, lines.ctypes.data_as(_vp), lines.size,
+                                                  off.ctypes.data_as(_vp), off.size - 1,
+                                                  F_PREPROCESS if preprocess else 0, ctypes.byref(t)),
+                  "zs_server_submit_compress")
+        return int(t.value)
+
+    def wait(self, ticket):
+        r = Reply()
+        _check_rc(lib().zs_server_wait(self.handle, ticket, ctypes.byref(r)), "zs_server_wait")
+        n = int(r.n)
+        off = np.ctypeslib.as_array(r.off, shape=(n + 1,)).copy()
+        data = np.ctypeslib.as_array(r.data, shape=(int(r.bytes),)).copy() if r.bytes else \
+            np.zeros(0, dtype=np.uint8)
+        t = {"submit": r.t_submit, "admit": r.t_admit, "done": r.t_done, "footprint": int(r.footprint)}
+        code, fb = int(r.code), int(r.first_bad)
+        lib().zs_server_release(self.handle, ticket)
+        return code, fb, data, off, t
+
+    def stats(self):
+        st = ServerStats()
+        _check_rc(lib().zs_server_get_stats(self.handle, ctypes.byref(st)), "zs_server_get_stats")
+        return st.as_dict()
+
+    def close(self):
+        if self.handle:
+            lib().zs_server_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

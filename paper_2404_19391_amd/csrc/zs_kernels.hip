@@ -2011,6 +2011,11 @@ constexpr int kIndexWgPerCu = 8;
 uint32_t tiles_for(uint64_t n, uint64_t per) { return (uint32_t)((n + per - 1) / per); }
 size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
+// Most workgroups a plain compression of n lines launches (sizes its workspace).
+size_t compress_grid_cap(uint64_t n, int cus) {
+    return std::min<size_t>((size_t)cus * kCompressWgPerCu, std::max<size_t>(1, tiles_for(n, kCL)));
+}
+
 // Jobs with at most this many tiles run as one decompression launch with a
 // look-back; larger ones as sizes -> scan -> emit.
 constexpr uint32_t kLookbackTiles = 1024;
@@ -2024,7 +2029,7 @@ size_t ws_bytes_for(int op, uint64_t n) {
         case ZS_OP_COMPRESS: {
             uint32_t nt = tiles_for(n, kCL);
             size_t st = ((size_t)nt * 8 + 255) & ~(size_t)255;
-            size_t grid = (size_t)cus * kCompressWgPerCu;
+            size_t grid = compress_grid_cap(n, cus);
             return h + st + grid * kWG * kGenLane + grid * kCapSmall;
         }
         case ZS_OP_DECOMPRESS:
@@ -2074,7 +2079,7 @@ BinnedWs binned_ws(void* ws, uint64_t n, uint64_t out_cap, int cus) {
     w.max_tiles = (uint32_t)(n / kMinLpt + kMaxBins + 1);
     w.nchunks = tiles_for(n, kBinChunk);
     w.ptiles = tiles_for(n, kCL);
-    const size_t grid = (size_t)cus * kCompressWgPerCu;
+    const size_t grid = std::min<size_t>((size_t)cus * kCompressWgPerCu, w.max_tiles);
     w.h1 = (WsHeader*)take(sizeof(WsHeader));
     w.h2 = (WsHeader*)take(sizeof(WsHeader));
     w.plan = (BinPlan*)take(sizeof(BinPlan));
@@ -2228,7 +2233,7 @@ zs_status zs_compress(const zs_dict* d, const uint8_t* in, uint64_t in_bytes, co
     uint64_t* status = (uint64_t*)(h + 1);
     size_t st_bytes = ((size_t)ntiles * 8 + 255) & ~(size_t)255;
     uint8_t* gen = (uint8_t*)status + st_bytes;
-    uint8_t* slots = gen + (size_t)di.cus * kCompressWgPerCu * kWG * kGenLane;
+    uint8_t* slots = gen + compress_grid_cap(n_lines, di.cus) * kWG * kGenLane;
     if (launch_init(h, status, ntiles, (ResultOut*)res, s) != ZS_OK) return ZS_EDEVICE;
     CompressArgs a;
     a.tables = d->d_tables;

@@ -149,6 +149,7 @@ def test_errors_compress(zs, gd, odict):
     # ENOSPC with no bad line; size-only mode gives the same offsets
     good, goff2 = oracle.join_lines([b"CCO", b"c1ccccc1"] * 300)
     b2, o2 = dev(good, goff2)
+    ws = zs.Workspaces().get(zs.OP_COMPRESS, goff2.size - 1)  # workspaces grow with the line count
     sizes = torch.empty(o2.numel(), dtype=torch.int64, device="cuda")
     res = zs.new_result()
     zs.compress_into(gd, b2, o2, None, sizes, ws, res)
