@@ -50,6 +50,8 @@ def parse():
     ap.add_argument("--serve-gb", type=float, default=50.0, help="compressed shard bytes resident (GB)")
     ap.add_argument("--shard-lines", type=int, default=40_000_000)
     ap.add_argument("--slots", type=int, default=16)
+    ap.add_argument("--probe-copy", action="store_true",
+                    help="after the timed steps, one plain 1 GiB device copy (scales the HBM byte counters)")
     ap.add_argument("--tune-lines", type=int, default=1_000_000, help="sample the autotuner times (uneven)")
     return ap.parse_args()
 
@@ -94,6 +96,34 @@ def cpu_baseline(buf, off, n_sample):
         "seconds": round(t2 - t0, 2),
         "cpu": cpu_model(),
     }
+
+
+KERNEL_SOURCES = ["paper_2404_19391_amd/csrc/zs_kernels.hip", "paper_2404_19391_amd/csrc/zs_common.hpp",
+                  "paper_2404_19391_amd/csrc/zs_tables.hpp", "paper_2404_19391_amd/csrc/zs_dict.cpp"]
+
+
+def kernel_source_hash():
+    import hashlib
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def measured_traffic(kernel):
+    """HBM bytes per launch of `kernel` from the committed counter summary, if it was taken
+    from the kernel sources as they are now; else None."""
+    path = os.path.join(ROOT, "profiles", "traffic.json")
+    try:
+        with open(path) as f:
+            t = json.load(f)
+    except (OSError, ValueError):
+        return None
+    e = t.get(kernel)
+    if not e or e.get("source_sha256") != kernel_source_hash():
+        return None
+    return e.get("bytes_per_launch")
 
 
 def time_ms(fn, stream, reps):
@@ -539,8 +569,16 @@ def main():
 
     roof = {"kernel": "compress_kernel", "bound": "hbm",
             "achieved": round(comp_hbm, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": round(comp_hbm / HBM_PEAK_GBS, 4), "traffic": None,
+            "frac": round(comp_hbm / HBM_PEAK_GBS, 4), "traffic": measured_traffic("compress_kernel"),
             "alg_bytes_per_launch": comp_alg, "avg_launch_ms": round(mean["compress"], 4)}
+    if args.probe_copy:
+        # a plain copy of known size, for the counter scale factor of the HBM byte counters
+        src = torch.empty(1 << 30, dtype=torch.uint8, device=dev)
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src.view(torch.int8))  # a dtype cast: an elementwise kernel (not a DMA copy), same bits
+        torch.cuda.synchronize()
+        del src, dst
 
     out = {
         "metric": METRIC,

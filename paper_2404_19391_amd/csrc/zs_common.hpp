@@ -246,6 +246,45 @@ __device__ inline void load_range(const uint8_t* src, uint64_t limit, uint64_t l
     }
 }
 
+// LDS stage writer of one thread: appends its bytes in order from stage index
+// s0.  Whole dwords that hold only this thread's bytes are written as dwords,
+// the partial ones at the two ends byte by byte (the neighbouring threads
+// write the rest of them).
+struct StageWriter {
+    uint8_t* stage;
+    uint32_t s0, s, a;
+    uint64_t acc;  // bytes [a, s) not yet written; s - a < 4 between calls
+    __device__ __forceinline__ void begin(uint8_t* st, uint32_t at) {
+        stage = st;
+        s0 = s = at;
+        a = at & ~3u;
+        acc = 0;
+    }
+    __device__ __forceinline__ void put_dword(uint32_t at, uint32_t v) {
+        if (at >= s0) {
+            *(uint32_t*)(stage + at) = v;
+        } else {
+#pragma unroll
+            for (int j = 0; j < 4; j++)
+                if (at + j >= s0) stage[at + j] = (uint8_t)(v >> (8 * j));
+        }
+    }
+    // m (1..4) bytes: the low bytes of v, its other bytes zero
+    __device__ __forceinline__ void add(uint32_t v, uint32_t m) {
+        acc |= (uint64_t)v << (8 * (s - a));
+        s += m;
+        if (s - a >= 4) {
+            put_dword(a, (uint32_t)acc);
+            acc >>= 32;
+            a += 4;
+        }
+    }
+    __device__ __forceinline__ void finish() {
+        for (uint32_t x = a; x < s; x++)
+            if (x >= s0) stage[x] = (uint8_t)(acc >> (8 * (x - a)));
+    }
+};
+
 // Copy a deferred tile's bytes from its global slot to out[base, base+total),
 // through an LDS stage shifted to the destination's 16-byte alignment.  The
 // stage must hold total + 15 bytes.

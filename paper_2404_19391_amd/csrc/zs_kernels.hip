@@ -49,12 +49,13 @@ constexpr int kCL = 256;              // lines per tile at most (one per thread)
 // their pre-processed form: the default variant runs 3 workgroups per CU, the
 // large one (long lines) 2.
 constexpr int kCapSmall = 14336;
+constexpr int kCapGather = 13312;  // binned short bins: room for the ABS array at 3 workgroups per CU
 constexpr int kCapLarge = 26624;
-constexpr int kSlots = 16;            // fast ring table (registers): up to 16 open rings, found by label
+constexpr int kSlots = 8;             // fast ring table (registers): up to 8 open rings, found by label
 constexpr int kGenLane = 400;         // per-lane ring tables in global memory (any line):
                                       // 100 open positions u16 + 100 last-close u16
-static_assert(kCapSmall >= 3 * (int)ZS_MAX_LINE, "a pre-processed line must fit");
-static_assert(kCapSmall >= (int)ZS_MAX_LINE + 1 + 16, "a raw line must fit");
+static_assert(kCapGather >= 3 * (int)ZS_MAX_LINE, "a pre-processed line must fit");
+static_assert(kCapGather >= (int)ZS_MAX_LINE + 1 + 16, "a raw line must fit");
 constexpr uint64_t kAbsBad = 1ull << 63;  // ABS flag (binned mode): the line's framing is bad
 
 constexpr uint8_t kSkip = 0x7F;    // marker: byte dropped by pre-processing
@@ -63,8 +64,9 @@ constexpr uint32_t kBadLine = 0x8000u;  // LENS flag: the line is bad (empty out
 
 struct CompressLds {
     uint32_t tab_bytes;  // dictionary part staged
-    uint32_t raw, pre, esc, off, abs, cost, eoff, lens, perm, misc;
-    uint32_t total;
+    uint32_t raw, pre, esc, off, cost, eoff, lens, perm, misc, abs;
+    uint32_t total;         // plain mode
+    uint32_t total_gather;  // binned mode (ABS at the end)
 };
 
 __host__ __device__ inline CompressLds compress_lds(uint32_t tab_bytes, uint32_t cap) {
@@ -75,13 +77,14 @@ __host__ __device__ inline CompressLds compress_lds(uint32_t tab_bytes, uint32_t
     L.pre = o;  o += cap;
     L.esc = o;  o += cap / 8;
     L.off = o;  o += align16((kCL + 1) * 8);
-    L.abs = o;  o += align16(kCL * 8);
     L.cost = o; o += kCL * 4;
     L.eoff = o; o += kCL * 4;
     L.lens = o; o += kCL * 2;
     L.perm = o; o += kCL * 2;
     L.misc = o; o += 256;
     L.total = align16(o);
+    L.abs = L.total;  // only binned launches allocate it
+    L.total_gather = L.abs + align16(kCL * 8);
     return L;
 }
 
@@ -705,6 +708,33 @@ struct Compressor {
         uint32_t ic = 0;
         bool nl_done = !st.in;
         uint64_t oc = st.in ? gbase + EOFF()[b0 + st.j] : 0;
+        if (gb1 - gb0 <= (uint64_t)(kRawCap - 16)) {
+            // the batch's output fits one window: each lane appends its line
+            // (codes, escapes, newline) with dword stores
+            const uintptr_t a0 = rel ? 0 : (((uintptr_t)(A.out + gb0)) & ~(uintptr_t)15);
+            const uintptr_t sbase = rel ? 0 : (uintptr_t)A.out - a0;
+            if (st.in) {
+                StageWriter wr;
+                wr.begin(stage, (uint32_t)(sbase + oc));
+                while (ic < m) {
+                    const uint32_t pos = st.P + ic;
+                    const uint32_t t = pre[pos];
+                    if ((esc[pos >> 5] >> (pos & 31)) & 1u) {
+                        wr.add(0x20u | (t << 8), 2);
+                        ic += 1;
+                    } else {
+                        wr.add(t, 1);
+                        ic += LENT[t];
+                    }
+                }
+                wr.add('\n', 1);
+                wr.finish();
+            }
+            __syncthreads();
+            if (!rel) flush_stage(A.out, gb0, gb1, a0, stage);
+            __syncthreads();
+            return;
+        }
         uint64_t wlo = gb0;
         while (wlo < gb1) {
             uint64_t whi = wlo + (uint64_t)(min(kRawCap, kPreCap) - 16);
@@ -987,39 +1017,6 @@ struct Decoder {
     __device__ __forceinline__ uint32_t* MISC() { return (uint32_t*)(smem + L.misc); }
     __device__ __forceinline__ uint8_t* STAGE() { return smem + L.stage; }
 
-    // Stage writer of one thread: appends its bytes in order from stage index
-    // s0; whole dwords that hold only this thread's bytes are written as
-    // dwords, the partial ones at the two ends byte by byte (the neighbours
-    // write the rest of them).
-    struct Writer {
-        uint8_t* stage;
-        uint32_t s0, s, a;
-        uint64_t acc;  // bytes [a, s) not yet written, s - a < 4 between calls
-        __device__ __forceinline__ void put_dword(uint32_t at, uint32_t v) {
-            if (at >= s0) {
-                *(uint32_t*)(stage + at) = v;
-            } else {
-#pragma unroll
-                for (int j = 0; j < 4; j++)
-                    if (at + j >= s0) stage[at + j] = (uint8_t)(v >> (8 * j));
-            }
-        }
-        // m (1..4) bytes: the low bytes of v, the others zero
-        __device__ __forceinline__ void add(uint32_t v, uint32_t m) {
-            acc |= (uint64_t)v << (8 * (s - a));
-            s += m;
-            if (s - a >= 4) {
-                put_dword(a, (uint32_t)acc);
-                acc >>= 32;
-                a += 4;
-            }
-        }
-        __device__ __forceinline__ void finish() {
-            for (uint32_t x = a; x < s; x++)
-                if (x >= s0) stage[x] = (uint8_t)(acc >> (8 * (x - a)));
-        }
-    };
-
     // One pass over the bytes [cb_lo, cb_hi) of lines [b0, b1) (Sec. IV-C: a
     // byte is a literal iff an odd run of spaces precedes it; a code expands to
     // its dictionary string).  Every line ends with its newline in CB.  Gives
@@ -1144,11 +1141,8 @@ struct Decoder {
             if (emit && sum) {
                 const int32_t st0 = sbase + (int32_t)pos0;
                 if (st0 >= 0 && st0 + (int32_t)sum <= kDStage) {
-                    Writer wr;
-                    wr.stage = stage;
-                    wr.s0 = wr.s = (uint32_t)st0;
-                    wr.a = wr.s0 & ~3u;
-                    wr.acc = 0;
+                    StageWriter wr;
+                    wr.begin(stage, (uint32_t)st0);
 #pragma unroll
                     for (int k = 0; k < 16; k++) {
                         const uint32_t len = (lp[k >> 2] >> (8 * (k & 3))) & 0xFFu;
@@ -2148,11 +2142,16 @@ zs_status zs_dict_create(const uint8_t* len, const uint8_t* exp, zs_dict** out) 
         return ZS_EDEVICE;
     }
     const int ls = (int)compress_lds(d->comp_bytes, kCapSmall).total;
-    const int ll = (int)compress_lds(d->comp_bytes, kCapLarge).total;
+    const int lg = (int)compress_lds(d->comp_bytes, kCapGather).total_gather;
+    const int ll = (int)compress_lds(d->comp_bytes, kCapLarge).total_gather;
     if (hipFuncSetAttribute((const void*)compress_kernel<8, kCapSmall>, hipFuncAttributeMaxDynamicSharedMemorySize,
                             ls) != hipSuccess ||
         hipFuncSetAttribute((const void*)compress_kernel<16, kCapSmall>, hipFuncAttributeMaxDynamicSharedMemorySize,
                             ls) != hipSuccess ||
+        hipFuncSetAttribute((const void*)compress_kernel<8, kCapGather>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                            lg) != hipSuccess ||
+        hipFuncSetAttribute((const void*)compress_kernel<16, kCapGather>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                            lg) != hipSuccess ||
         hipFuncSetAttribute((const void*)compress_kernel<8, kCapLarge>, hipFuncAttributeMaxDynamicSharedMemorySize,
                             ll) != hipSuccess ||
         hipFuncSetAttribute((const void*)compress_kernel<16, kCapLarge>, hipFuncAttributeMaxDynamicSharedMemorySize,
@@ -2199,11 +2198,17 @@ static zs_status launch_init(WsHeader* h, uint64_t* status, uint32_t ntiles, Res
 // max_tiles workgroups.
 static zs_status launch_compress(const zs_dict* d, const CompressArgs& a, bool large, uint32_t max_tiles, int cus,
                                  hipStream_t s) {
-    const uint32_t lds = compress_lds(d->comp_bytes, large ? kCapLarge : kCapSmall).total;
-    const void* kfn = large ? (d->lk == 8 ? (const void*)compress_kernel<8, kCapLarge>
-                                          : (const void*)compress_kernel<16, kCapLarge>)
-                            : (d->lk == 8 ? (const void*)compress_kernel<8, kCapSmall>
-                                          : (const void*)compress_kernel<16, kCapSmall>);
+    // plain: kCapSmall; binned: kCapGather, or kCapLarge for the bins that ask for it
+    const int cap = large ? kCapLarge : (a.ids ? kCapGather : kCapSmall);
+    const CompressLds cl = compress_lds(d->comp_bytes, cap);
+    const uint32_t lds = a.ids ? cl.total_gather : cl.total;
+    const bool k8 = d->lk == 8;
+    const void* kfn = cap == kCapLarge   ? (k8 ? (const void*)compress_kernel<8, kCapLarge>
+                                              : (const void*)compress_kernel<16, kCapLarge>)
+                      : cap == kCapGather ? (k8 ? (const void*)compress_kernel<8, kCapGather>
+                                                : (const void*)compress_kernel<16, kCapGather>)
+                                          : (k8 ? (const void*)compress_kernel<8, kCapSmall>
+                                                : (const void*)compress_kernel<16, kCapSmall>);
     int occ = 0;
     if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, kfn, kWG, lds) != hipSuccess || occ < 1) occ = 1;
     if (occ > kCompressWgPerCu) occ = kCompressWgPerCu;
