@@ -41,7 +41,7 @@ def parse():
     ap.add_argument("--seed", type=int, default=2)
     ap.add_argument("--ra-batches", type=int, default=200)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
-    ap.add_argument("--cpu-lines", type=int, default=120_000)
+    ap.add_argument("--cpu-lines", type=int, default=800_000)
     ap.add_argument("--only", default="", help="comma list of ops to run (profiling runs)")
     ap.add_argument("--workload", default="bulk", choices=["bulk", "uneven", "serve"],
                     help="bulk: the headline step; uneven: plain vs length-binned / autotuned / graph "

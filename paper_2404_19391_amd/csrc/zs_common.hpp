@@ -246,6 +246,13 @@ __device__ inline void load_range(const uint8_t* src, uint64_t limit, uint64_t l
     }
 }
 
+// Per 4-byte word: bit 7 of each byte set where the byte equals the same byte
+// of pat (exact: no carries cross bytes).
+__device__ inline uint32_t swar_eq_bytes(uint32_t w, uint32_t pat) {
+    const uint32_t x = w ^ pat;
+    return ~(((x & 0x7F7F7F7Fu) + 0x7F7F7F7Fu) | x) & 0x80808080u;
+}
+
 // LDS stage writer of one thread: appends its bytes in order from stage index
 // s0.  Whole dwords that hold only this thread's bytes are written as dwords,
 // the partial ones at the two ends byte by byte (the neighbouring threads

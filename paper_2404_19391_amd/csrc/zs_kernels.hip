@@ -1026,8 +1026,13 @@ struct Decoder {
     // Lines marked in BAD produce only their newline when mask_bad is set.
     // Bytes that make a line corrupt mark it in BAD and set *err.  Returns the
     // output bytes of the batch.
+    //
+    // clean: the batch has no bad line and exactly one newline per line, so the
+    // lines end at the newlines: line indices come from a count of newlines, and
+    // a piece with no space and no escape reaching into it is measured with
+    // byte-parallel arithmetic.
     __device__ __forceinline__ uint32_t pass(uint32_t b0, uint32_t b1, uint32_t cb_lo, uint32_t cb_hi, bool mask_bad,
-                                             bool emit, int32_t sbase, bool* err, bool* spill) {
+                                             bool emit, int32_t sbase, bool* err, bool* spill, bool clean) {
         const uint32_t tid = threadIdx.x;
         const uint8_t* cb = CB();
         const uint32_t* qoff = QOFF();
@@ -1035,7 +1040,7 @@ struct Decoder {
         uint32_t* llen = LLEN();
         uint8_t* stage = STAGE();
         uint32_t* psc = MISC() + kDmScanA;
-        uint32_t carry_pos = 0;
+        uint32_t carry_pos = 0, carry_nl = 0;
         bool err_any = false, spill_any = false;
         const uint32_t c0 = cb_lo & ~15u;
         for (uint32_t seg = c0; seg < cb_hi; seg += kSeg) {
@@ -1078,58 +1083,119 @@ struct Decoder {
                     if (tr < 16 || y <= cb_lo) break;
                 }
             }
-            // the line of the first valid byte
-            uint32_t q = b0, nb = 0;
-            if (valid) {
-                const uint32_t xs = x0 + (uint32_t)__builtin_ctz(valid);  // the first valid byte
-                uint32_t l = b0, h = b1;
-                while (h - l > 1) {
-                    const uint32_t mid = (l + h) >> 1;
-                    if (qoff[mid] <= xs) l = mid;
-                    else h = mid;
-                }
-                q = l;
-                nb = qoff[q + 1];
-            }
-            const uint32_t qfirst = q;
-            bool qbad = mask_bad && valid && bad[q] != 0;
-            uint32_t sum = 0, term = 0, lit = 0;
+            uint32_t sum = 0, term = 0, lit = 0, qfirst = b0, errm_pending = 0;
+            if (clean) {
+                uint32_t errm = 0;
+                if (sp == 0 && !(r & 1)) {
+                    // no escape: byte-parallel lengths, newlines, undefined codes
 #pragma unroll
-            for (int k = 0; k < 16; k++) {
-                const uint32_t x = x0 + k;
-                const bool isv = (valid >> k) & 1;
-                if (isv && x >= nb) {
-                    do {
-                        q++;
-                        nb = qoff[q + 1];
-                    } while (x >= nb);
-                    qbad = mask_bad && bad[q] != 0;
+                    for (int i = 0; i < 4; i++) {
+                        const uint32_t vb = (valid >> (4 * i)) & 0xFu;
+                        const uint32_t vm = ((vb * 0x00204081u) & 0x01010101u) * 0xFFu;
+                        const uint32_t nlw = swar_eq_bytes(wv[i], 0x0A0A0A0Au) & vm & 0x80808080u;
+                        const uint32_t nl1 = nlw >> 7;
+                        const uint32_t lenw = ((lp[i] & ~(nl1 * 0xFFu)) | nl1) & vm;
+                        const uint32_t erw = swar_eq_bytes(lp[i], 0u) & ~nlw & vm & 0x80808080u;
+                        lp[i] = lenw;
+                        sum += (lenw * 0x01010101u) >> 24;
+                        term |= ((nl1 | (nl1 >> 7) | (nl1 >> 14) | (nl1 >> 21)) & 0xFu) << (4 * i);
+                        const uint32_t e1 = erw >> 7;
+                        errm |= ((e1 | (e1 >> 7) | (e1 >> 14) | (e1 >> 21)) & 0xFu) << (4 * i);
+                    }
+                } else {
+#pragma unroll
+                    for (int k = 0; k < 16; k++) {
+                        const bool isv = (valid >> k) & 1;
+                        const uint32_t ck = ZS_BYTE(k);
+                        const uint32_t tl = (lp[k >> 2] >> (8 * (k & 3))) & 0xFFu;
+                        const bool iss = (sp >> k) & 1;
+                        const bool ist = isv && ck == '\n';
+                        const bool islit = isv && (r & 1);
+                        uint32_t len;
+                        bool e = false;
+                        if (!isv) len = 0;
+                        else if (ist) { len = 1; e = islit; }
+                        else if (islit) { len = 1; e = ck < 0x20u || ck > 0x7Eu; }
+                        else if (iss) len = 0;
+                        else { len = tl; e = tl == 0; }
+                        errm |= (e ? 1u : 0u) << k;
+                        term |= (ist ? 1u : 0u) << k;
+                        lit |= (islit && !ist ? 1u : 0u) << k;
+                        lp[k >> 2] = (lp[k >> 2] & ~(0xFFu << (8 * (k & 3)))) | (len << (8 * (k & 3)));
+                        sum += len;
+                        r = iss ? r + 1 : 0u;
+                    }
                 }
-                const uint32_t ck = ZS_BYTE(k);
-                const uint32_t tl = (lp[k >> 2] >> (8 * (k & 3))) & 0xFFu;
-                const bool iss = (sp >> k) & 1;
-                const bool ist = isv && (x + 1 == nb);
-                const bool islit = isv && (r & 1);
-                uint32_t len;
-                bool e = false;
-                if (!isv) len = 0;
-                else if (qbad) len = ist ? 1u : 0u;
-                else if (ist) { len = 1; e = islit; }                         // a dangling escape
-                else if (islit) { len = 1; e = ck < 0x20u || ck > 0x7Eu; }    // literal outside 0x20..0x7E
-                else if (iss) len = 0;
-                else { len = tl; e = tl == 0; }                              // undefined code
-                if (e) {
-                    bad[q] = (uint8_t)kErrCorrupt;
-                    err_any = true;
+                if (errm) {
+                    err_any = true;  // lines marked once the newlines before each byte are known
+                    errm_pending = errm;
                 }
-                term |= (ist ? 1u : 0u) << k;
-                lit |= (islit && !ist ? 1u : 0u) << k;
-                lp[k >> 2] = (lp[k >> 2] & ~(0xFFu << (8 * (k & 3)))) | (len << (8 * (k & 3)));
-                sum += len;
-                r = iss ? r + 1 : 0u;
+            } else {
+                // the line of the first valid byte
+                uint32_t q = b0, nb = 0;
+                if (valid) {
+                    const uint32_t xs = x0 + (uint32_t)__builtin_ctz(valid);  // the first valid byte
+                    uint32_t l = b0, h = b1;
+                    while (h - l > 1) {
+                        const uint32_t mid = (l + h) >> 1;
+                        if (qoff[mid] <= xs) l = mid;
+                        else h = mid;
+                    }
+                    q = l;
+                    nb = qoff[q + 1];
+                }
+                qfirst = q;
+                bool qbad = mask_bad && valid && bad[q] != 0;
+#pragma unroll
+                for (int k = 0; k < 16; k++) {
+                    const uint32_t x = x0 + k;
+                    const bool isv = (valid >> k) & 1;
+                    if (isv && x >= nb) {
+                        do {
+                            q++;
+                            nb = qoff[q + 1];
+                        } while (x >= nb);
+                        qbad = mask_bad && bad[q] != 0;
+                    }
+                    const uint32_t ck = ZS_BYTE(k);
+                    const uint32_t tl = (lp[k >> 2] >> (8 * (k & 3))) & 0xFFu;
+                    const bool iss = (sp >> k) & 1;
+                    const bool ist = isv && (x + 1 == nb);
+                    const bool islit = isv && (r & 1);
+                    uint32_t len;
+                    bool e = false;
+                    if (!isv) len = 0;
+                    else if (qbad) len = ist ? 1u : 0u;
+                    else if (ist) { len = 1; e = islit; }                         // a dangling escape
+                    else if (islit) { len = 1; e = ck < 0x20u || ck > 0x7Eu; }    // literal outside 0x20..0x7E
+                    else if (iss) len = 0;
+                    else { len = tl; e = tl == 0; }                              // undefined code
+                    if (e) {
+                        bad[q] = (uint8_t)kErrCorrupt;
+                        err_any = true;
+                    }
+                    term |= (ist ? 1u : 0u) << k;
+                    lit |= (islit && !ist ? 1u : 0u) << k;
+                    lp[k >> 2] = (lp[k >> 2] & ~(0xFFu << (8 * (k & 3)))) | (len << (8 * (k & 3)));
+                    sum += len;
+                    r = iss ? r + 1 : 0u;
+                }
             }
             uint32_t segtot;
-            const uint32_t pos0 = carry_pos + block_excl_scan(sum, psc, &segtot);
+            // clean batches: the newlines ride along in the scan (bits 18 and up)
+            const uint32_t scan = block_excl_scan(clean ? (sum | ((uint32_t)__popc(term) << 18)) : sum, psc, &segtot);
+            const uint32_t pos0 = carry_pos + (clean ? (scan & 0x3FFFFu) : scan);
+            if (clean) {
+                qfirst = b0 + carry_nl + (scan >> 18);
+                if (errm_pending) {
+                    for (uint32_t m = errm_pending; m; m &= m - 1) {
+                        const uint32_t k = (uint32_t)__builtin_ctz(m);
+                        bad[qfirst + __popc(term & ((1u << k) - 1u))] = (uint8_t)kErrCorrupt;
+                    }
+                }
+                carry_nl += segtot >> 18;
+                segtot &= 0x3FFFFu;
+            }
             if (term) {
                 uint32_t qq = qfirst, pos = pos0;
 #pragma unroll
@@ -1193,11 +1259,11 @@ struct Decoder {
     // Size a loaded batch: one pass, and a second one with the lines found
     // corrupt masked.  Reports the corrupt lines.
     __device__ __forceinline__ uint32_t size_batch(uint32_t b0, uint32_t b1, uint32_t cb_lo, uint32_t cb_hi,
-                                                   bool anybad) {
+                                                   bool anybad, bool clean) {
         bool err;
-        uint32_t T = pass(b0, b1, cb_lo, cb_hi, anybad, false, 0, &err, nullptr);
+        uint32_t T = pass(b0, b1, cb_lo, cb_hi, anybad, false, 0, &err, nullptr, clean);
         if (err) {
-            T = pass(b0, b1, cb_lo, cb_hi, true, false, 0, &err, nullptr);
+            T = pass(b0, b1, cb_lo, cb_hi, true, false, 0, &err, nullptr, false);
             const uint32_t q = b0 + threadIdx.x;
             if (q < b1 && BAD()[q] == kErrCorrupt) note_error(A.ws, r0 + q, kErrCorrupt);
         }
@@ -1210,14 +1276,14 @@ struct Decoder {
     // whose output exceeds the stage goes out in several windows.  Returns the
     // batch's output bytes; line ends are left in LLEN.
     __device__ __forceinline__ uint32_t decode_batch(uint32_t b0, uint32_t b1, uint32_t cb_lo, uint32_t cb_hi,
-                                                     bool anybad, uint64_t g0, bool write) {
+                                                     bool anybad, bool clean, uint64_t g0, bool write) {
         bool err, spill;
         const uintptr_t dst = (uintptr_t)(A.out + g0);
         const uintptr_t a0 = dst & ~(uintptr_t)15;
         const int32_t lead = (int32_t)(dst - a0);
-        uint32_t T = pass(b0, b1, cb_lo, cb_hi, anybad, write, lead, &err, &spill);
+        uint32_t T = pass(b0, b1, cb_lo, cb_hi, anybad, write, lead, &err, &spill, clean);
         if (err) {
-            T = pass(b0, b1, cb_lo, cb_hi, true, write, lead, &err, &spill);
+            T = pass(b0, b1, cb_lo, cb_hi, true, write, lead, &err, &spill, false);
             const uint32_t q = b0 + threadIdx.x;
             if (q < b1 && BAD()[q] == kErrCorrupt) note_error(A.ws, r0 + q, kErrCorrupt);
         }
@@ -1229,7 +1295,7 @@ struct Decoder {
         // window w holds destination bytes [a0 + w kDStage, a0 + (w + 1) kDStage)
         for (uint32_t w = 0;; w++) {
             const uint64_t wlo = (uint64_t)w * kDStage;  // relative to a0
-            if (w > 0) pass(b0, b1, cb_lo, cb_hi, true, true, lead - (int32_t)wlo, &err, &spill);
+            if (w > 0) pass(b0, b1, cb_lo, cb_hi, true, true, lead - (int32_t)wlo, &err, &spill, false);
             const int64_t wrel = (int64_t)wlo - lead;  // batch position of the window's first byte
             uint64_t lo = (uint64_t)max(wrel, (int64_t)0), hi = (uint64_t)(wrel + kDStage);
             if (hi > T) hi = T;
@@ -1299,14 +1365,14 @@ struct Decoder {
             uint32_t tpos = 0, b0 = 0;
             while (b0 < nl) {
                 uint32_t b1, cb_lo, cb_hi;
-                bool anybad;
-                load_batch(b0, nl, regular, gather, &b1, &cb_lo, &cb_hi, &anybad);
+                bool anybad, clean;
+                load_batch(b0, nl, regular, gather, &b1, &cb_lo, &cb_hi, &anybad, &clean);
                 uint32_t T;
                 if (emit_phase) {
-                    T = decode_batch(b0, b1, cb_lo, cb_hi, anybad, gbase + tpos, A.out && fits);
+                    T = decode_batch(b0, b1, cb_lo, cb_hi, anybad, clean, gbase + tpos, A.out && fits);
                     write_offsets(b0, b1, gbase + tpos);
                 } else {
-                    T = size_batch(b0, b1, cb_lo, cb_hi, anybad);
+                    T = size_batch(b0, b1, cb_lo, cb_hi, anybad, clean);
                 }
                 tpos += T;
                 b0 = b1;
@@ -1330,14 +1396,15 @@ struct Decoder {
             bool regular;
             const uint32_t nl = setup_tile(t, &regular);
             uint32_t tpos = 0, b0 = 0, nb = 0, T = 0, lo = 0, hi = 0, lb1 = 0;
-            bool lbad = false;
+            bool lbad = false, lclean = false;
             while (b0 < nl) {
                 uint32_t b1;
-                bool anybad;
-                load_batch(b0, nl, regular, gather, &b1, &lo, &hi, &anybad);
-                T = size_batch(b0, b1, lo, hi, anybad);
+                bool anybad, clean;
+                load_batch(b0, nl, regular, gather, &b1, &lo, &hi, &anybad, &clean);
+                T = size_batch(b0, b1, lo, hi, anybad, clean);
                 lb1 = b1;
                 lbad = anybad;
+                lclean = clean;
                 // line ends relative to the tile
                 const uint32_t q = b0 + tid;
                 if (q < b1) llen[q] += tpos;
@@ -1359,15 +1426,15 @@ struct Decoder {
             if (A.out && fits) {
                 if (nb == 1) {
                     __syncthreads();
-                    decode_batch(0, lb1, lo, hi, lbad, gbase, true);
+                    decode_batch(0, lb1, lo, hi, lbad, lclean, gbase, true);
                 } else {
                     uint32_t g = 0;
                     b0 = 0;
                     while (b0 < nl) {
                         uint32_t b1;
-                        bool anybad;
-                        load_batch(b0, nl, regular, gather, &b1, &lo, &hi, &anybad);
-                        g += decode_batch(b0, b1, lo, hi, anybad, gbase + g, true);
+                        bool anybad, clean;
+                        load_batch(b0, nl, regular, gather, &b1, &lo, &hi, &anybad, &clean);
+                        g += decode_batch(b0, b1, lo, hi, anybad, clean, gbase + g, true);
                         b0 = b1;
                         __syncthreads();
                     }
@@ -1383,7 +1450,7 @@ struct Decoder {
     // last byte is not a newline is bad, and its last CB byte is made one so
     // that escape runs never cross lines).
     __device__ __forceinline__ void load_batch(uint32_t b0, uint32_t nl, bool regular, bool gather, uint32_t* b1_out,
-                                               uint32_t* cb_lo, uint32_t* cb_hi, bool* anybad) {
+                                               uint32_t* cb_lo, uint32_t* cb_hi, bool* anybad, bool* clean) {
         const uint32_t tid = threadIdx.x;
         uint32_t* misc = MISC();
         uint8_t* bad = BAD();
@@ -1472,6 +1539,21 @@ struct Decoder {
             isbad = bad[q] != 0;
         }
         *anybad = __syncthreads_or(isbad) != 0;
+        // clean: no bad line and no newline inside a line (one newline per line)
+        {
+            const uint32_t lo = qoff[b0], hi = qoff[b1];
+            uint32_t nnl = 0;
+            for (uint32_t x0 = (lo & ~15u) + tid * 16; x0 < hi; x0 += kWG * 16) {
+                const uint4 v = *(const uint4*)(cb + x0);
+                const uint32_t wv[4] = {v.x, v.y, v.z, v.w};
+#pragma unroll
+                for (int k = 0; k < 16; k++)
+                    nnl += (x0 + k >= lo && x0 + k < hi && ((wv[k >> 2] >> (8 * (k & 3))) & 0xFFu) == '\n') ? 1u : 0u;
+            }
+            uint32_t tot;
+            block_excl_scan(nnl, misc + kDmScanB, &tot);
+            *clean = !*anybad && tot == b1 - b0;
+        }
         *b1_out = b1;
         *cb_lo = qoff[b0];
         *cb_hi = qoff[b1];
