@@ -292,6 +292,42 @@ struct StageWriter {
     }
 };
 
+// Copy a parked tile's total bytes from its global slot (16-byte aligned,
+// readable up to total + 16 bytes) to out[base, base + total) directly: each
+// thread loads the two slot chunks that one 16-byte chunk of the destination
+// straddles, shifts them into place and stores 16 bytes (byte stores at the
+// two partial ends).
+__device__ inline void copy_slot_direct(uint8_t* out, const uint8_t* slot, uint32_t total, uint64_t base) {
+    const uintptr_t dst = (uintptr_t)(out + base);
+    const uintptr_t a0 = dst & ~(uintptr_t)15;
+    const int32_t lead = (int32_t)(dst - a0);
+    const uint32_t nch = ((uint32_t)lead + total + 15) >> 4;
+    const uint4* s16 = (const uint4*)slot;
+    for (uint32_t c = threadIdx.x; c < nch; c += kWG) {
+        const int32_t sb = (int32_t)(c * 16) - lead;  // slot byte of the chunk's first byte
+        const int32_t i0 = sb >> 4;                   // arithmetic: -1 for the first chunk when lead > 0
+        const uint32_t sh = (uint32_t)sb & 15u;
+        const uint4 A = i0 >= 0 ? s16[i0] : make_uint4(0, 0, 0, 0);
+        const uint4 B = (uint32_t)(i0 + 1) * 16u < total ? s16[i0 + 1] : make_uint4(0, 0, 0, 0);
+        const uint32_t w[8] = {A.x, A.y, A.z, A.w, B.x, B.y, B.z, B.w};
+        const uint32_t q = sh >> 2, r = sh & 3u;
+        uint32_t d[5];
+#pragma unroll
+        for (int j = 0; j < 5; j++) d[j] = q == 0 ? w[j] : q == 1 ? w[j + 1] : q == 2 ? w[j + 2] : w[j + 3];
+        uint32_t o[4];
+#pragma unroll
+        for (int j = 0; j < 4; j++) o[j] = __builtin_amdgcn_alignbyte(d[j + 1], d[j], r);
+        uint8_t* p = (uint8_t*)(a0 + ((uintptr_t)c << 4));
+        if (sb >= 0 && sb + 16 <= (int32_t)total) {
+            *(uint4*)p = make_uint4(o[0], o[1], o[2], o[3]);
+        } else {
+#pragma unroll
+            for (int k = 0; k < 16; k++)
+                if (sb + k >= 0 && sb + k < (int32_t)total) p[k] = (uint8_t)(o[k >> 2] >> (8 * (k & 3)));
+        }
+    }
+}
+
 // Copy a deferred tile's bytes from its global slot to out[base, base+total),
 // through an LDS stage shifted to the destination's 16-byte alignment.  The
 // stage must hold total + 15 bytes.

@@ -789,7 +789,7 @@ struct Compressor {
         const uint32_t tid = threadIdx.x;
         uint8_t* slot = A.slots + (uint64_t)blockIdx.x * kSlotBytes;
         bool pend = false;
-        uint32_t pt = 0, pnl = 0, ptotal = 0;
+        uint32_t pt = 0, pnl = 0, ptotal = 0, prel = 0;
         uint64_t pk0 = 0;
         while (true) {
             uint32_t t, nl = 0;
@@ -868,9 +868,9 @@ struct Compressor {
                 }
                 __syncthreads();
                 const uint64_t pbase = ((uint64_t*)misc)[6];
-                if (tid < pnl) A.out_off[pk0 + tid + 1] += pbase;
+                if (tid < pnl) A.out_off[pk0 + tid + 1] = pbase + prel;
                 if (A.out) {
-                    if (pbase + ptotal <= A.out_cap) copy_slot_out(A.out, slot, ptotal, pbase, stage);
+                    if (pbase + ptotal <= A.out_cap) copy_slot_direct(A.out, slot, ptotal, pbase);
                     else if (tid == 0) atomicOr(&A.ws->enospc, 1u);
                 }
                 pend = false;
@@ -880,7 +880,7 @@ struct Compressor {
             if (t == 0 && tid == 0) A.out_off[0] = 0;
             const bool defer = nb == 1 && total + 16 <= (uint32_t)kSlotBytes;
             if (defer) {
-                if (tid < nl) A.out_off[k0 + tid + 1] = e + mylen;  // tile-relative for now
+                prel = e + mylen;  // this line's end inside the tile, until the tile is placed
                 if (A.out) {
                     emit(0, nl, st, 0, true);
                     for (uint32_t c = tid; c < (total + 15) / 16; c += kWG)
@@ -942,7 +942,7 @@ constexpr int kDL = 256;                 // lines (or requests) per tile
 constexpr int kCbCap = 8192 + 16;        // LDS bytes of compressed lines per batch
 constexpr uint32_t kMaxCLine = 8191;     // longest compressed line accepted (newline excluded)
 constexpr int kSeg = kWG * 16;           // bytes per decode segment
-constexpr int kDStage = 24576;           // LDS output stage (a multiple of 16)
+constexpr int kDStage = 16384;           // LDS output stage (a multiple of 16)
 
 // Phases of a decompression call.  Large jobs run sizes -> scan of the tile
 // totals -> emit, with no workgroup ever waiting for another; small jobs (few
@@ -1347,10 +1347,10 @@ struct Decoder {
 
     // Sizes and emission with the tile's base known (kPhaseSizes, kPhaseEmit).
     // Tiles are taken in a fixed order; no workgroup waits for another.
+    template <bool emit_phase>
     __device__ __forceinline__ void run_static() {
         const uint32_t tid = threadIdx.x;
         const bool gather = A.ids != nullptr;
-        const bool emit_phase = A.phase == kPhaseEmit;
         for (uint32_t t = blockIdx.x; t < A.ntiles; t += gridDim.x) {
             bool regular;
             const uint32_t nl = setup_tile(t, &regular);
@@ -1560,7 +1560,11 @@ struct Decoder {
     }
 };
 
-__global__ void __launch_bounds__(kWG) decompress_kernel(DecompressArgs a) {
+// One instantiation per phase, so that each gets its own register allocation
+// (the sizes phase carries no emission code).
+template <int PH>
+__global__ void __launch_bounds__(kWG) __attribute__((amdgpu_waves_per_eu(PH == kPhaseSizes ? 6 : 1)))
+decompress_kernel(DecompressArgs a) {
     extern __shared__ __align__(16) uint8_t smem[];
     {
         // header + LEN at [0, 320), EXP at [320, 320 + 4096), in 16-byte pieces
@@ -1577,8 +1581,8 @@ __global__ void __launch_bounds__(kWG) decompress_kernel(DecompressArgs a) {
     }
     __syncthreads();
     Decoder d(a, smem);
-    if (a.phase == kPhaseLookback) d.run_lookback();
-    else d.run_static();
+    if constexpr (PH == kPhaseLookback) d.run_lookback();
+    else d.run_static<PH == kPhaseEmit>();
 }
 
 // Exclusive prefix of n per-tile totals: base[i] = total[0] + ... + total[i-1],
@@ -2238,8 +2242,10 @@ zs_status zs_dict_create(const uint8_t* len, const uint8_t* exp, zs_dict** out) 
                             ll) != hipSuccess ||
         hipFuncSetAttribute((const void*)compress_kernel<16, kCapLarge>, hipFuncAttributeMaxDynamicSharedMemorySize,
                             ll) != hipSuccess ||
-        hipFuncSetAttribute((const void*)decompress_kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
-                            (int)decompress_lds().total) != hipSuccess) {
+        hipFuncSetAttribute((const void*)decompress_kernel<kPhaseEmit>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                            (int)decompress_lds().total) != hipSuccess ||
+        hipFuncSetAttribute((const void*)decompress_kernel<kPhaseLookback>,
+                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)decompress_lds().total) != hipSuccess) {
         (void)hipFree(d->d_tables);
         delete d;
         return ZS_EDEVICE;
@@ -2661,10 +2667,9 @@ static zs_status decompress_common(const zs_dict* d, const uint8_t* in, uint64_t
     a.tile_base = tile_base;
     a.res = (ResultOut*)res;
     const DecompressLds dl = decompress_lds();
-    auto grid_for = [&](uint32_t lds, int cap) {
+    auto grid_for = [&](const void* kfn, uint32_t lds, int cap) {
         int occ = 0;
-        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, (const void*)decompress_kernel, kWG, lds) != hipSuccess ||
-            occ < 1)
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, kfn, kWG, lds) != hipSuccess || occ < 1)
             occ = 1;
         if (occ > cap) occ = cap;
         uint32_t g = (uint32_t)di.cus * (uint32_t)occ;
@@ -2672,14 +2677,20 @@ static zs_status decompress_common(const zs_dict* d, const uint8_t* in, uint64_t
     };
     if (small) {
         a.phase = kPhaseLookback;
-        hipLaunchKernelGGL(decompress_kernel, dim3(grid_for(dl.total, kDecompressWgPerCu)), dim3(kWG), dl.total, s, a);
+        hipLaunchKernelGGL(decompress_kernel<kPhaseLookback>,
+                           dim3(grid_for((const void*)decompress_kernel<kPhaseLookback>, dl.total, kDecompressWgPerCu)),
+                           dim3(kWG), dl.total, s, a);
     } else {
         a.phase = kPhaseSizes;
-        hipLaunchKernelGGL(decompress_kernel, dim3(grid_for(dl.total_sizes, kDecompressSizesWgPerCu)), dim3(kWG),
-                           dl.total_sizes, s, a);
+        hipLaunchKernelGGL(decompress_kernel<kPhaseSizes>,
+                           dim3(grid_for((const void*)decompress_kernel<kPhaseSizes>, dl.total_sizes,
+                                         kDecompressSizesWgPerCu)),
+                           dim3(kWG), dl.total_sizes, s, a);
         hipLaunchKernelGGL(tile_scan_kernel, dim3(1), dim3(kScanWG), 0, s, tile_total, tile_base, ntiles);
         a.phase = kPhaseEmit;
-        hipLaunchKernelGGL(decompress_kernel, dim3(grid_for(dl.total, kDecompressWgPerCu)), dim3(kWG), dl.total, s, a);
+        hipLaunchKernelGGL(decompress_kernel<kPhaseEmit>,
+                           dim3(grid_for((const void*)decompress_kernel<kPhaseEmit>, dl.total, kDecompressWgPerCu)),
+                           dim3(kWG), dl.total, s, a);
     }
     return hipGetLastError() == hipSuccess ? ZS_OK : ZS_EDEVICE;
 }
