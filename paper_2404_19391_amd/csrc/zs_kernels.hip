@@ -64,7 +64,7 @@ constexpr uint32_t kBadLine = 0x8000u;  // LENS flag: the line is bad (empty out
 
 struct CompressLds {
     uint32_t tab_bytes;  // dictionary part staged
-    uint32_t raw, pre, esc, off, cost, eoff, lens, perm, misc, abs;
+    uint32_t raw, pre, esc, off, cost, eoff, lens, perm, misc, sink, ident, abs;
     uint32_t total;         // plain mode
     uint32_t total_gather;  // binned mode (ABS at the end)
 };
@@ -82,6 +82,8 @@ __host__ __device__ inline CompressLds compress_lds(uint32_t tab_bytes, uint32_t
     L.lens = o; o += kCL * 2;
     L.perm = o; o += kCL * 2;
     L.misc = o; o += 256;
+    L.sink = o; o += kCL;  // one byte per lane: stores of parse steps past the line's start
+    L.ident = o; o += 256; // ident[b] = b: an escaped byte is looked up like a code
     L.total = align16(o);
     L.abs = L.total;  // only binned launches allocate it
     L.total_gather = L.abs + align16(kCL * 8);
@@ -411,17 +413,23 @@ struct Compressor {
 
     // Steps K.. of one unrolled group: at step K the cost of position i+L sits in
     // slot (K - L) mod LK, and the new cost[i] replaces the oldest one, slot K.
+    // The steps have no branches: a lane whose line is done (it >= m) keeps
+    // stepping on bytes at or just before its line start, but stores into its
+    // sink byte and keeps its costs, so that the group is one block the
+    // scheduler can interleave.  Escapes are collected in *escm.
     template <int K>
     __device__ __forceinline__ void parse_steps(ParseState& ps, uint8_t* buf, uint32_t base, uint32_t m,
-                                                uint32_t top) {
+                                                uint32_t top, int32_t P, uint8_t* sink, uint32_t Cs,
+                                                uint32_t* escm) {
         if constexpr (K < LK) {
             const uint32_t it = base + K;
-            if (it < m) {
-                const uint32_t pos = top - it;
+            const bool act = it < m;
+            {
+                const int32_t pos = (int32_t)top - (int32_t)it;
                 const uint32_t s = ps.s;
                 // the next state and the byte two places back are independent of the DP below
-                const uint32_t sn = TRANS[__umul24(s, C) + ps.coln];
-                const uint32_t cnn = buf[(int)pos - 2];  // may read just before the line: any byte will do
+                const uint32_t sn = TRANS[__umul24(s, Cs) + ps.coln];
+                const uint32_t cnn = buf[max(pos, P) - 2];  // may read just before the line: any byte will do
                 const uint32_t colnn = COL[cnn];
                 const uint32_t* ok = OUTK + s * LK;
                 uint32_t Kmin = ps.V[(K + LK - 1) % LK] + 63u;  // escape: cost[i+1] + 2, low bits 31
@@ -432,17 +440,19 @@ struct Compressor {
                     Kmin = min(Kmin, min(ps.V[(K + 2 * LK - 3 - q) % LK] | kv.z, ps.V[(K + 2 * LK - 4 - q) % LK] | kv.w));
                 }
                 const uint32_t ch = 31u - (Kmin & 31u);
-                const uint32_t caddr = (ch >= 2) ? (off_code + s * LK + ch - 1) : (off_code1 + ps.c);
-                const uint32_t t = smem[caddr];
-                buf[pos] = (uint8_t)((ch == 0) ? ps.c : t);
-                if (ch == 0) atomicOr(&ESC()[pos >> 5], 1u << (pos & 31));
-                ps.V[K] = (Kmin | 31u) + 1u;
+                // the byte to store, always one load: the code of length ch, the
+                // one-byte code of c, or (escape) c itself
+                const uint32_t tb = (ch >= 2) ? off_code + s * LK - 1 : (ch == 1) ? off_code1 : L.ident;
+                const uint32_t t = smem[tb + ((ch >= 2) ? ch : ps.c)];
+                *(act ? buf + pos : sink) = (uint8_t)t;
+                *escm |= ((act && ch == 0) ? 1u : 0u) << K;
+                ps.V[K] = act ? (Kmin | 31u) + 1u : ps.V[K];
                 ps.s = sn;
                 ps.c = ps.cn;
                 ps.cn = cnn;
                 ps.coln = colnn;
             }
-            parse_steps<K + 1>(ps, buf, base, m, top);
+            parse_steps<K + 1>(ps, buf, base, m, top, P, sink, Cs, escm);
         }
     }
 
@@ -678,8 +688,15 @@ struct Compressor {
             ps.s = TRANS[COL[ps.c]];
             ps.cn = buf[(int)top - 1];
             ps.coln = COL[ps.cn];
+            uint8_t* sink = smem + L.sink + threadIdx.x;
+            const uint32_t Cs = __builtin_amdgcn_readfirstlane(C);
             for (uint32_t base = 0; base < mx; base += LK) {
-                parse_steps<0>(ps, buf, base, m, top);
+                uint32_t escm = 0;
+                parse_steps<0>(ps, buf, base, m, top, (int32_t)st.P, sink, Cs, &escm);
+                for (; escm; escm &= escm - 1) {  // rare: bytes with no code of their own
+                    const uint32_t pos = top - (base + (uint32_t)__builtin_ctz(escm));
+                    atomicOr(&ESC()[pos >> 5], 1u << (pos & 31));
+                }
             }
             if (m) {
                 const uint32_t last = (m - 1) & (LK - 1);
@@ -928,6 +945,7 @@ __global__ void __launch_bounds__(kWG) compress_kernel(CompressArgs a) {
         const uint4* src = (const uint4*)a.tables;
         uint4* dst = (uint4*)smem;
         for (uint32_t k = threadIdx.x; k < a.tab_bytes / 16; k += kWG) dst[k] = src[k];
+        smem[compress_lds(a.tab_bytes, CAP).ident + threadIdx.x] = (uint8_t)threadIdx.x;
     }
     __syncthreads();
     Compressor<LK, CAP> c(a, smem);
