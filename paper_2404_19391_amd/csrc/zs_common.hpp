@@ -36,11 +36,14 @@ __device__ inline void note_error(WsHeader* h, uint64_t index, uint32_t kind) {
 //      prefix through this tile).
 constexpr uint64_t kFlagAgg = 1ull << 62, kFlagInc = 2ull << 62, kValMask = (1ull << 62) - 1;
 
+// The words carry sizes only: no workgroup reads data another one wrote, so
+// relaxed device-scope atomics suffice.  (Acquire/release at device scope
+// would write back and invalidate the XCD's L2 at every access.)
 __device__ inline void status_store(uint64_t* p, uint64_t v) {
-    __hip_atomic_store(p, v, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 __device__ inline uint64_t status_load(uint64_t* p) {
-    return __hip_atomic_load(p, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
 __device__ inline uint64_t wave_sum64(uint64_t v) {

@@ -247,7 +247,8 @@ struct Compressor {
     // Forward scan of one raw line, four bytes at a time with byte-parallel
     // masks (one flag bit per byte, at bit 7 of each byte): bad bytes, bracket
     // depth, ring labels - a digit outside brackets, or '%' outside brackets
-    // followed by two digits (Sec. II).  Label positions go to `list` (u16).
+    // followed by two digits (Sec. II).  Labels go to `list` (u16: position in
+    // the line << 4, low bits the digit, or 15 for a '%' label).
     __device__ static inline uint32_t eq_bytes(uint32_t w, uint32_t pat) {
         const uint32_t x = w ^ pat;
         return ~(((x & 0x7F7F7F7Fu) + 0x7F7F7F7Fu) | x) & 0x80808080u;
@@ -303,7 +304,10 @@ struct Compressor {
 #pragma unroll
                 for (int k = 0; k < 4; k++) {
                     if (lab & (0x80u << (8 * k))) {
-                        if (nlab < cap) list[nlab] = (uint16_t)(w + k - R);
+                        // entry: line position << 4 | digit value, or 15 for '%'
+                        const uint32_t cb = (word >> (8 * k)) & 0xFFu;
+                        const uint32_t dv = (cb == '%') ? 15u : cb - '0';
+                        if (nlab < cap) list[nlab] = (uint16_t)(((w + k - R) << 4) | dv);
                         else over = true;
                         nlab++;
                     }
@@ -326,29 +330,32 @@ struct Compressor {
     // an ID reaches 32; returns false when rings stay open.
     __device__ __forceinline__ bool ring_fast(uint8_t* raw, uint32_t R, const uint16_t* list, uint32_t nlab, uint32_t maxlab,
                               int* delta, bool* overflow, bool* marked) {
+        // slot word of an open ring: (position + 1) << 8 | ('%' label) << 7 | label
         bool mk_any = false;
         uint32_t os[kSlots], mk[kSlots];
 #pragma unroll
         for (int k = 0; k < kSlots; k++) { os[k] = 0; mk[k] = 0; }
         int dl = 0, opens = 0;
         bool ovf = false;
+        uint32_t nxt = list[0];
         for (uint32_t q = 0; q < maxlab; q++) {
+            const uint32_t ent = nxt;
+            nxt = list[q + 1];  // next entry ahead of time (past the end: unused bytes of PRE)
             if (q < nlab && !ovf) {
-                const uint32_t p = list[q];
-                const uint32_t c0 = raw[R + p];
+                const uint32_t p = ent >> 4;
                 uint32_t v, tl;
-                if (c0 == '%') {
+                if ((ent & 15u) == 15u) {
                     v = (raw[R + p + 1] - '0') * 10u + (raw[R + p + 2] - '0');
                     tl = 3;
                 } else {
-                    v = c0 - '0';
+                    v = ent & 15u;
                     tl = 1;
                 }
                 // the open ring of label v, else the first free slot
                 uint32_t slot = kSlots, freeslot = kSlots;
 #pragma unroll
                 for (int k = kSlots - 1; k >= 0; k--) {
-                    slot = (os[k] != 0 && (os[k] & 0xFFu) == v) ? (uint32_t)k : slot;
+                    slot = (os[k] != 0 && (os[k] & 0x7Fu) == v) ? (uint32_t)k : slot;
                     freeslot = (os[k] == 0) ? (uint32_t)k : freeslot;
                 }
                 uint32_t e = 0, m = 0;
@@ -366,11 +373,11 @@ struct Compressor {
                 } else if (e == 0) {
 #pragma unroll
                     for (int k = 0; k < kSlots; k++) {
-                        os[k] = (slot == (uint32_t)k) ? (((p + 1) << 8) | v) : os[k];
+                        os[k] = (slot == (uint32_t)k) ? (((p + 1) << 8) | (tl == 3 ? 0x80u : 0u) | v) : os[k];
                         mk[k] = (slot == (uint32_t)k) ? 0u : mk[k];
                     }
                     opens++;
-                } else if ((e & 0xFFu) == v) {
+                } else if ((e & 0x7Fu) == v) {
                     const uint32_t o = (e >> 8) - 1;
                     const uint32_t id = (uint32_t)__builtin_ctz(~m);
                     if (m == 0xFFFFFFFFu) {
@@ -383,7 +390,7 @@ struct Compressor {
                             mk[k] |= bit;
                         }
                         opens--;
-                        const uint32_t to = (raw[R + o] == '%') ? 3u : 1u;
+                        const uint32_t to = (e & 0x80u) ? 3u : 1u;
                         const int nlen = id < 10 ? 1 : 3;
                         // a one-byte label that stays one byte takes its new digit in place;
                         // anything else is marked for the expansion pass
@@ -501,10 +508,10 @@ struct Compressor {
     __device__ __forceinline__ uint32_t batch(uint64_t k0, uint32_t nl, uint32_t b0, bool regular, LineState& st) {
         uint32_t* misc = MISC();
         uint64_t* off = OFF();
-        uint16_t* lens = LENS();
-        uint16_t* perm = PERM();
         uint8_t* raw = RAW();
         uint8_t* pre = PRE();
+        uint16_t* lens = LENS();
+        uint16_t* perm = PERM();
         const uint32_t tid = threadIdx.x;
         const bool prep = (A.flags & ZS_F_PREPROCESS) != 0;
         // ---- extent of the batch
@@ -580,8 +587,12 @@ struct Compressor {
                 if (tid < nb) perm[cnt[32 + bk] + within] = (uint16_t)tid;
             }
             __syncthreads();
-            st.in = tid < nb;
-            st.j = st.in ? perm[tid] : 0u;
+            // wave w takes the ((w + rot) mod 4)-th quarter of the length order:
+            // the wave with the longest lines moves from tile to tile, so that
+            // it does not sit on the same SIMD in every workgroup of the CU
+            const uint32_t rq = (tid + 64u * (blockIdx.x + ((uint32_t)k0 >> 8))) & (kWG - 1);
+            st.in = rq < nb;
+            st.j = st.in ? perm[rq] : 0u;
             const uint32_t lj = st.in ? lens[st.j] : 0u;
             st.bad = st.in && (lj & kBadLine);
             st.len = (st.in && !st.bad) ? lj : 0u;
