@@ -263,9 +263,11 @@ struct Compressor {
         bool over = false;
         const uint32_t end = R + len;
         const uint32_t w0 = R & ~3u;
+        // two words in flight ahead of the one being classified
         uint32_t word = *(const uint32_t*)(raw + w0);
+        uint32_t next = *(const uint32_t*)(raw + w0 + 4);
         for (uint32_t w = w0; w < end; w += 4) {
-            const uint32_t next = *(const uint32_t*)(raw + w + 4);
+            const uint32_t next2 = *(const uint32_t*)(raw + w + 8);
             // flag bits of the bytes of this word that belong to the line
             // (clamps in signed arithmetic: see the note at the decoder's valid mask)
             const uint32_t lo = (uint32_t)max((int32_t)R - (int32_t)w, 0), hi = min(end - w, 4u);
@@ -314,6 +316,7 @@ struct Compressor {
                 }
             }
             word = next;
+            next = next2;
         }
         *nlab_out = nlab;
         *corrupt_out = bad != 0;
@@ -1980,29 +1983,46 @@ __global__ void __launch_bounds__(kWG) index_count_kernel(IndexArgs a) {
     }
 }
 
-// Write phase: the same loads, newline masks kept in registers, the eight
-// round counts scanned together, offsets written in order from the tile's
-// base.
+// The newline flags (bit 7 of each byte, from newline_bits) of a 4-byte word
+// as 4 bits: a multiply gathers bits 0, 8, 16, 24 at bits 21..24 (no two
+// partial products overlap).
+__device__ inline uint32_t compact4(uint32_t nl) { return (((nl >> 7) * 0x00204081u) >> 21) & 0xFu; }
+
+constexpr int kIdxLdsCap = kIdxTile / 4;  // newline positions of a tile staged in LDS (u16 each)
+
+// Write phase: the same loads, one 16-bit newline mask per round in registers,
+// the eight round counts scanned together.  Each newline's tile-relative
+// position goes to LDS at its rank, then the tile's offsets are written as one
+// contiguous, coalesced run; a tile with more newlines than the LDS holds
+// writes them from the masks directly.
 __global__ void __launch_bounds__(kWG) index_write_kernel(IndexArgs a) {
     __shared__ uint32_t sc[kWaves][kIdxRounds];
+    __shared__ uint16_t pos[kIdxLdsCap];
     const uint32_t tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
     const bool aligned = (((uintptr_t)a.buf) & 15) == 0;
     for (uint32_t t = blockIdx.x; t < a.ntiles; t += gridDim.x) {
         const uint64_t tb = (uint64_t)t * kIdxTile;
-        uint32_t mask[4 * kIdxRounds], cnt[kIdxRounds], ex[kIdxRounds];
+        uint32_t m16[kIdxRounds], ex[kIdxRounds];
+        uint4 v[kIdxRounds];
+        if (aligned && tb + kIdxTile <= a.len) {  // the whole tile in bounds: plain loads
 #pragma unroll
-        for (int k = 0; k < kIdxRounds; k++) {
-            const uint4 v = load16_or_pad(a.buf, a.len, tb + 4096u * k + 16u * tid, aligned);
-            mask[4 * k + 0] = newline_bits(v.x);
-            mask[4 * k + 1] = newline_bits(v.y);
-            mask[4 * k + 2] = newline_bits(v.z);
-            mask[4 * k + 3] = newline_bits(v.w);
-            cnt[k] = __popc(mask[4 * k]) + __popc(mask[4 * k + 1]) + __popc(mask[4 * k + 2]) + __popc(mask[4 * k + 3]);
+            for (int k = 0; k < kIdxRounds; k++) v[k] = *(const uint4*)(a.buf + tb + 4096u * k + 16u * tid);
+        } else {  // the last tile or an unaligned buffer: one round at a time
+#pragma unroll
+            for (int k = 0; k < kIdxRounds; k++) {
+                v[k] = load16_or_pad(a.buf, a.len, tb + 4096u * k + 16u * tid, aligned);
+                __builtin_amdgcn_sched_barrier(0);
+            }
         }
 #pragma unroll
+        for (int k = 0; k < kIdxRounds; k++)
+            m16[k] = compact4(newline_bits(v[k].x)) | (compact4(newline_bits(v[k].y)) << 4) |
+                     (compact4(newline_bits(v[k].z)) << 8) | (compact4(newline_bits(v[k].w)) << 12);
+#pragma unroll
         for (int k = 0; k < kIdxRounds; k++) {
-            const uint32_t inc = wave_incl_scan(cnt[k]);
-            ex[k] = inc - cnt[k];
+            const uint32_t c = __popc(m16[k]);
+            const uint32_t inc = wave_incl_scan(c);
+            ex[k] = inc - c;
             if (lane == 63) sc[w][k] = inc;
         }
         __syncthreads();
@@ -2020,18 +2040,26 @@ __global__ void __launch_bounds__(kWG) index_write_kernel(IndexArgs a) {
             tot += round;
         }
         const uint64_t sbase = a.tile_base[t];
+        if (tot <= (uint32_t)kIdxLdsCap) {
 #pragma unroll
-        for (int k = 0; k < kIdxRounds; k++) {
-            uint64_t k1 = sbase + ex[k];
-            const uint64_t x = tb + 4096u * k + 16u * tid;
+            for (int k = 0; k < kIdxRounds; k++) {
+                uint32_t j = ex[k];
+                const uint32_t p0 = 4096u * k + 16u * tid + 1u;  // tile offset just past byte 0 of the piece
+                for (uint32_t m = m16[k]; m; m &= m - 1) pos[j++] = (uint16_t)(p0 + (uint32_t)__builtin_ctz(m));
+            }
+            __syncthreads();
+            for (uint32_t i = tid; i < tot; i += kWG) {
+                const uint64_t k1 = sbase + 1 + i;
+                if (k1 < a.off_cap) a.off[k1] = tb + pos[i];
+            }
+        } else {
 #pragma unroll
-            for (int q = 0; q < 4; q++) {
-                uint32_t m = mask[4 * k + q];
-                while (m) {
-                    const int bit = __builtin_ctz(m);
-                    m &= m - 1;
+            for (int k = 0; k < kIdxRounds; k++) {
+                uint64_t k1 = sbase + ex[k];
+                const uint64_t x = tb + 4096u * k + 16u * tid + 1u;
+                for (uint32_t m = m16[k]; m; m &= m - 1) {
                     k1++;
-                    if (k1 < a.off_cap) a.off[k1] = x + 4 * q + (bit >> 3) + 1;
+                    if (k1 < a.off_cap) a.off[k1] = x + (uint32_t)__builtin_ctz(m);
                 }
             }
         }
