@@ -1034,11 +1034,13 @@ struct Decoder {
     DecompressLds L;
     const uint8_t* LEN;
     const uint8_t* EXP;
+    bool lmax8;  // every expansion fits 8 bytes
 
     __device__ Decoder(const DecompressArgs& a, uint8_t* s) : A(a), smem(s) {
         L = decompress_lds();
         LEN = smem + 64;
         EXP = smem + 64 + 256;
+        lmax8 = ((const TableHeader*)smem)->lmax <= 8;
     }
     __device__ __forceinline__ uint8_t* CB() { return smem + L.cb; }
     __device__ __forceinline__ uint32_t* QOFF() { return (uint32_t*)(smem + L.qoff); }
@@ -1116,9 +1118,11 @@ struct Decoder {
                 }
             }
             uint32_t sum = 0, term = 0, lit = 0, qfirst = b0, errm_pending = 0;
+            bool swar = false;  // lengths from the byte-parallel path: no escape in the piece
             if (clean) {
                 uint32_t errm = 0;
                 if (sp == 0 && !(r & 1)) {
+                    swar = true;
                     // no escape: byte-parallel lengths, newlines, undefined codes
 #pragma unroll
                     for (int i = 0; i < 4; i++) {
@@ -1238,7 +1242,38 @@ struct Decoder {
             }
             if (emit && sum) {
                 const int32_t st0 = sbase + (int32_t)pos0;
-                if (st0 >= 0 && st0 + (int32_t)sum <= kDStage) {
+                if (st0 >= 0 && st0 + (int32_t)sum <= kDStage && swar && lmax8) {
+                    // every byte is a code of at most 8 bytes (a newline's row
+                    // of EXP holds a newline; rows are zero past their length):
+                    // the run is built with funnel shifts and stored by dwords,
+                    // bytes only in the two dwords shared with the neighbours
+                    uint32_t* st32 = (uint32_t*)stage;
+                    const uint32_t s0 = (uint32_t)st0, lead = s0 & 3u, a0 = s0 >> 2;
+                    uint32_t a = a0, p = lead, acc = 0;
+#pragma unroll
+                    for (int k = 0; k < 16; k++) {
+                        const uint32_t len = (lp[k >> 2] >> (8 * (k & 3))) & 0xFFu;
+                        uint2 e = *(const uint2*)(EXP + ZS_BYTE(k) * kExpStride);
+                        if (len == 0) e = make_uint2(0, 0);  // a byte outside the batch adds nothing
+                        const uint32_t sh = 8 * p;
+                        const uint32_t c0 = acc | (e.x << sh);
+                        const uint32_t c1 = p ? __builtin_amdgcn_alignbit(e.y, e.x, 32 - sh) : e.y;
+                        const uint32_t c2 = p ? (e.y >> (32 - sh)) : 0u;
+                        const uint32_t n = p + len;
+                        if (n >= 4) {
+                            if (a == a0 && lead) {
+                                for (uint32_t j = lead; j < 4; j++) stage[4 * a + j] = (uint8_t)(c0 >> (8 * j));
+                            } else {
+                                st32[a] = c0;
+                            }
+                        }
+                        if (n >= 8) st32[a + 1] = c1;
+                        acc = n >= 8 ? c2 : (n >= 4 ? c1 : c0);
+                        a += n >> 2;
+                        p = n & 3u;
+                    }
+                    for (uint32_t j = (a == a0 ? lead : 0u); j < p; j++) stage[4 * a + j] = (uint8_t)(acc >> (8 * j));
+                } else if (st0 >= 0 && st0 + (int32_t)sum <= kDStage) {
                     StageWriter wr;
                     wr.begin(stage, (uint32_t)st0);
 #pragma unroll
@@ -1608,7 +1643,9 @@ decompress_kernel(DecompressArgs a) {
             if (k < 4) src = 16 * k;
             else if (k < 20) src = off_len + 16 * (k - 4);
             else src = off_exp + 16 * (k - 20);
-            dst[k] = *(const uint4*)(a.tables + src);
+            // the row of byte '\n' (never a code) holds a newline, for the
+            // decoder's byte-parallel path
+            dst[k] = (k == 20 + '\n') ? make_uint4('\n', 0, 0, 0) : *(const uint4*)(a.tables + src);
         }
     }
     __syncthreads();
