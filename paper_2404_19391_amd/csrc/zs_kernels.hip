@@ -139,6 +139,7 @@ struct LineState {
     bool in;        // this lane holds a line of the batch
     bool bad;       // framing or byte error: the output line is empty
     bool simple;    // batch-wide: no line changed length, tokens live in RAW, stage is PRE
+    bool esc;       // batch-wide: some byte was escaped (the ESC bits are needed)
 };
 
 __device__ inline void restore_line(uint8_t* raw, uint32_t R, const uint8_t* src, uint32_t len) {
@@ -687,6 +688,7 @@ struct Compressor {
         __syncthreads();
         // ---- parse (backward): automaton + (min,+) window over the next LK costs
         uint32_t cost = 0;
+        bool esc_any = false;
         {
             uint8_t* buf = st.simple ? raw : pre;
             const uint32_t m = (st.in && !st.bad) ? st.m : 0u;
@@ -707,6 +709,7 @@ struct Compressor {
             for (uint32_t base = 0; base < mx; base += LK) {
                 uint32_t escm = 0;
                 parse_steps<0>(ps, buf, base, m, top, (int32_t)st.P, sink, Cs, &escm);
+                esc_any |= escm != 0;
                 for (; escm; escm &= escm - 1) {  // rare: bytes with no code of their own
                     const uint32_t pos = top - (base + (uint32_t)__builtin_ctz(escm));
                     atomicOr(&ESC()[pos >> 5], 1u << (pos & 31));
@@ -721,7 +724,7 @@ struct Compressor {
             }
         }
         if (st.in) COST()[b0 + st.j] = st.bad ? 0u : cost;
-        __syncthreads();
+        st.esc = __syncthreads_or(esc_any) != 0;
         return b1;
     }
 
@@ -744,7 +747,32 @@ struct Compressor {
             // (codes, escapes, newline) with dword stores
             const uintptr_t a0 = rel ? 0 : (((uintptr_t)(A.out + gb0)) & ~(uintptr_t)15);
             const uintptr_t sbase = rel ? 0 : (uintptr_t)A.out - a0;
-            if (st.in) {
+            if (st.in && !st.esc) {
+                // one byte per code: a 32-bit accumulator, dword stores, bytes
+                // only in the dwords shared with the neighbouring lines
+                uint32_t* st32 = (uint32_t*)stage;
+                const uint32_t s0 = (uint32_t)(sbase + oc), lead = s0 & 3u, a0 = s0 >> 2;
+                uint32_t a = a0, p = lead, acc = 0;
+                auto put = [&]() {
+                    if (a == a0 && lead) {
+                        for (uint32_t j = lead; j < 4; j++) stage[4 * a + j] = (uint8_t)(acc >> (8 * j));
+                    } else {
+                        st32[a] = acc;
+                    }
+                    a++;
+                    p = 0;
+                    acc = 0;
+                };
+                while (ic < m) {
+                    const uint32_t t = pre[st.P + ic];
+                    acc |= t << (8 * p);
+                    ic += LENT[t];
+                    if (++p == 4) put();
+                }
+                acc |= (uint32_t)'\n' << (8 * p);
+                if (++p == 4) put();
+                for (uint32_t j = (a == a0 ? lead : 0u); j < p; j++) stage[4 * a + j] = (uint8_t)(acc >> (8 * j));
+            } else if (st.in) {
                 StageWriter wr;
                 wr.begin(stage, (uint32_t)(sbase + oc));
                 while (ic < m) {
@@ -850,6 +878,7 @@ struct Compressor {
             }
             LineState st;
             st.simple = true;
+            st.esc = true;
             st.in = false;
             st.bad = false;
             uint32_t nb = 0, total = 0, e = 0, mylen = 0;
