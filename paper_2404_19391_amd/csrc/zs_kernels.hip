@@ -52,6 +52,7 @@ constexpr int kCapSmall = 14336;
 constexpr int kCapGather = 13312;  // binned short bins: room for the ABS array at 3 workgroups per CU
 constexpr int kCapLarge = 26624;
 constexpr int kSlots = 8;             // fast ring table (registers): up to 8 open rings, found by label
+constexpr int kSlotsFirst = 4;        // the smaller table tried first
 constexpr int kGenLane = 400;         // per-lane ring tables in global memory (any line):
                                       // 100 open positions u16 + 100 last-close u16
 static_assert(kCapGather >= 3 * (int)ZS_MAX_LINE, "a pre-processed line must fit");
@@ -326,19 +327,20 @@ struct Compressor {
         *has_pct = pct_any != 0;
     }
 
-    // Ring IDs from the label list with a register table of kSlots open rings
+    // Ring IDs from the label list with a register table of NS open rings
     // (found by label value, free slots reused) and, per open ring, the bit set
     // of the IDs of the rings that closed inside it; a closing ring takes the
     // smallest ID not in its set (Sec. IV-A).  Markers are written over the
-    // raw line.  Sets *overflow when more than kSlots rings are open at once or
+    // raw line.  Sets *overflow when more than NS rings are open at once or
     // an ID reaches 32; returns false when rings stay open.
+    template <int NS>
     __device__ __forceinline__ bool ring_fast(uint8_t* raw, uint32_t R, const uint16_t* list, uint32_t nlab, uint32_t maxlab,
                               int* delta, bool* overflow, bool* marked) {
         // slot word of an open ring: (position + 1) << 8 | ('%' label) << 7 | label
         bool mk_any = false;
-        uint32_t os[kSlots], mk[kSlots];
+        uint32_t os[NS], mk[NS];
 #pragma unroll
-        for (int k = 0; k < kSlots; k++) { os[k] = 0; mk[k] = 0; }
+        for (int k = 0; k < NS; k++) { os[k] = 0; mk[k] = 0; }
         int dl = 0, opens = 0;
         bool ovf = false;
         uint32_t nxt = list[0];
@@ -356,27 +358,27 @@ struct Compressor {
                     tl = 1;
                 }
                 // the open ring of label v, else the first free slot
-                uint32_t slot = kSlots, freeslot = kSlots;
+                uint32_t slot = NS, freeslot = NS;
 #pragma unroll
-                for (int k = kSlots - 1; k >= 0; k--) {
+                for (int k = NS - 1; k >= 0; k--) {
                     slot = (os[k] != 0 && (os[k] & 0x7Fu) == v) ? (uint32_t)k : slot;
                     freeslot = (os[k] == 0) ? (uint32_t)k : freeslot;
                 }
                 uint32_t e = 0, m = 0;
-                if (slot == kSlots) {
+                if (slot == NS) {
                     slot = freeslot;
                 } else {
 #pragma unroll
-                    for (int k = 0; k < kSlots; k++) {
+                    for (int k = 0; k < NS; k++) {
                         e = (slot == (uint32_t)k) ? os[k] : e;
                         m = (slot == (uint32_t)k) ? mk[k] : m;
                     }
                 }
-                if (slot == kSlots) {
-                    ovf = true;  // more than kSlots rings open
+                if (slot == NS) {
+                    ovf = true;  // more than NS rings open
                 } else if (e == 0) {
 #pragma unroll
-                    for (int k = 0; k < kSlots; k++) {
+                    for (int k = 0; k < NS; k++) {
                         os[k] = (slot == (uint32_t)k) ? (((p + 1) << 8) | (tl == 3 ? 0x80u : 0u) | v) : os[k];
                         mk[k] = (slot == (uint32_t)k) ? 0u : mk[k];
                     }
@@ -389,7 +391,7 @@ struct Compressor {
                     } else {
                         const uint32_t bit = 1u << id;
 #pragma unroll
-                        for (int k = 0; k < kSlots; k++) {
+                        for (int k = 0; k < NS; k++) {
                             os[k] = (slot == (uint32_t)k) ? 0u : os[k];
                             mk[k] |= bit;
                         }
@@ -625,7 +627,14 @@ struct Compressor {
             for (int d = 32; d >= 1; d >>= 1) maxlab = max(maxlab, (uint32_t)__shfl_xor((int)maxlab, d, 64));
             bool marked = false;
             if (run_rings) {
-                const bool ok = ring_fast(raw, st.R, list, nlab, maxlab, &delta, &overflow, &marked);
+                // a table of 4 slots first (more rings than that are rarely open at
+                // once), 8 for the lines it cannot hold
+                bool ok = ring_fast<kSlotsFirst>(raw, st.R, list, nlab, maxlab, &delta, &overflow, &marked);
+                if (overflow) {
+                    restore_line(raw, st.R, line_src(line), st.len);
+                    overflow = false;
+                    ok = ring_fast<kSlots>(raw, st.R, list, nlab, maxlab, &delta, &overflow, &marked);
+                }
                 if (!ok && !overflow) {
                     malformed = true;
                     restore_line(raw, st.R, line_src(line), st.len);
