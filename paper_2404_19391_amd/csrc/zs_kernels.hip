@@ -1014,13 +1014,11 @@ constexpr uint32_t kMaxCLine = 8191;     // longest compressed line accepted (ne
 constexpr int kSeg = kWG * 16;           // bytes per decode segment
 constexpr int kDStage = 16384;           // LDS output stage (a multiple of 16)
 
-// Phases of a decompression call.  Large jobs run sizes -> scan of the tile
-// totals -> emit, with no workgroup ever waiting for another; small jobs (few
-// tiles) run one launch that places its tiles with a decoupled look-back.
-constexpr int kPhaseSizes = 0, kPhaseEmit = 1, kPhaseLookback = 2;
+// A decompression call is one launch: tiles are taken in ticket order, sized,
+// placed by a decoupled look-back and emitted.
 
 struct DecompressLds {
-    uint32_t tabs, cb, qoff, llen, bad, off, misc, stage, total, total_sizes;
+    uint32_t tabs, cb, qoff, llen, bad, off, misc, stage, total;
 };
 
 __host__ __device__ inline DecompressLds decompress_lds() {
@@ -1035,8 +1033,7 @@ __host__ __device__ inline DecompressLds decompress_lds() {
     o = align16(o);
     L.off = o;    o += (kDL + 1) * 16;  // a and b per line
     L.misc = o;   o += 256;
-    L.total_sizes = align16(o);         // the sizes phase needs nothing beyond this point
-    L.stage = L.total_sizes;
+    L.stage = align16(o);
     L.total = L.stage + kDStage;
     return L;
 }
@@ -1054,11 +1051,8 @@ struct DecompressArgs {
     uint64_t* out_off;
     uint32_t ntiles;
     uint32_t tl;                // lines (requests) per tile, at most kDL
-    int phase;
     WsHeader* ws;
-    uint64_t* status;           // look-back words (kPhaseLookback)
-    uint32_t* tile_total;       // output bytes per tile (written by kPhaseSizes)
-    const uint64_t* tile_base;  // exclusive prefix of tile_total, ntiles + 1 entries (read by kPhaseEmit)
+    uint64_t* status;           // look-back words, one per tile
     ResultOut* res;
 };
 
@@ -1450,46 +1444,8 @@ struct Decoder {
         if (q < b1) A.out_off[r0 + q + 1] = g + LLEN()[q];
     }
 
-    // Sizes and emission with the tile's base known (kPhaseSizes, kPhaseEmit).
-    // Tiles are taken in a fixed order; no workgroup waits for another.
-    template <bool emit_phase>
-    __device__ __forceinline__ void run_static() {
-        const uint32_t tid = threadIdx.x;
-        const bool gather = A.ids != nullptr;
-        for (uint32_t t = blockIdx.x; t < A.ntiles; t += gridDim.x) {
-            bool regular;
-            const uint32_t nl = setup_tile(t, &regular);
-            uint64_t gbase = 0;
-            bool fits = false;
-            if (emit_phase) {
-                gbase = A.tile_base[t];
-                fits = A.tile_base[t + 1] <= A.out_cap;
-                if (!fits && tid == 0) atomicOr(&A.ws->enospc, 1u);
-                if (t == 0 && tid == 0) A.out_off[0] = 0;
-            }
-            uint32_t tpos = 0, b0 = 0;
-            while (b0 < nl) {
-                uint32_t b1, cb_lo, cb_hi;
-                bool anybad, clean;
-                load_batch(b0, nl, regular, gather, &b1, &cb_lo, &cb_hi, &anybad, &clean);
-                uint32_t T;
-                if (emit_phase) {
-                    T = decode_batch(b0, b1, cb_lo, cb_hi, anybad, clean, gbase + tpos, A.out && fits);
-                    write_offsets(b0, b1, gbase + tpos);
-                } else {
-                    T = size_batch(b0, b1, cb_lo, cb_hi, anybad, clean);
-                }
-                tpos += T;
-                b0 = b1;
-                __syncthreads();
-            }
-            if (!emit_phase && tid == 0) A.tile_total[t] = tpos;
-        }
-        if (emit_phase) finish_workgroup(A.ws, A.res, gridDim.x);
-    }
-
-    // One launch for a few tiles (kPhaseLookback): tiles in ticket order, each
-    // placed by a decoupled look-back once its size is known.
+    // Tiles in ticket order, each placed by a decoupled look-back once its
+    // size is known.
     __device__ __forceinline__ void run_lookback() {
         uint32_t* misc = MISC();
         uint32_t* llen = LLEN();
@@ -1665,11 +1621,7 @@ struct Decoder {
     }
 };
 
-// One instantiation per phase, so that each gets its own register allocation
-// (the sizes phase carries no emission code).
-template <int PH>
-__global__ void __launch_bounds__(kWG) __attribute__((amdgpu_waves_per_eu(PH == kPhaseSizes ? 6 : 1)))
-decompress_kernel(DecompressArgs a) {
+__global__ void __launch_bounds__(kWG) decompress_kernel(DecompressArgs a) {
     extern __shared__ __align__(16) uint8_t smem[];
     {
         // header + LEN at [0, 320), EXP at [320, 320 + 4096), in 16-byte pieces
@@ -1688,8 +1640,7 @@ decompress_kernel(DecompressArgs a) {
     }
     __syncthreads();
     Decoder d(a, smem);
-    if constexpr (PH == kPhaseLookback) d.run_lookback();
-    else d.run_static<PH == kPhaseEmit>();
+    d.run_lookback();
 }
 
 // Exclusive prefix of n per-tile totals: base[i] = total[0] + ... + total[i-1],
@@ -2217,7 +2168,7 @@ DeviceInfo device_info() {
 }
 
 constexpr int kCompressWgPerCu = 4;  // upper bound of the persistent grid per CU (sizes the workspace)
-constexpr int kDecompressWgPerCu = 4;  // upper bound of the persistent grid per CU (sizes the workspace)
+constexpr int kDecompressWgPerCu = 4;  // upper bound of the persistent decompression grid per CU
 constexpr int kIndexWgPerCu = 8;
 
 uint32_t tiles_for(uint64_t n, uint64_t per) { return (uint32_t)((n + per - 1) / per); }
@@ -2228,10 +2179,6 @@ size_t compress_grid_cap(uint64_t n, int cus) {
     return std::min<size_t>((size_t)cus * kCompressWgPerCu, std::max<size_t>(1, tiles_for(n, kCL)));
 }
 
-// Jobs with at most this many tiles run as one decompression launch with a
-// look-back; larger ones as sizes -> scan -> emit.
-constexpr uint32_t kLookbackTiles = 1024;
-constexpr int kDecompressSizesWgPerCu = 8;
 
 size_t ws_bytes_for(int op, uint64_t n) {
     DeviceInfo di = device_info();
@@ -2247,7 +2194,7 @@ size_t ws_bytes_for(int op, uint64_t n) {
         case ZS_OP_DECOMPRESS:
         case ZS_OP_DECOMPRESS_LINES: {
             const size_t nt = tiles_for(n, 32);  // tiles may be as small as 32 lines
-            return h + align256(nt * 8) + align256(nt * 4) + (nt + 1) * 8;
+            return h + align256(nt * 8);
         }
         case ZS_OP_INDEX: {
             const size_t nt = tiles_for(n, kIdxTile);
@@ -2374,10 +2321,8 @@ zs_status zs_dict_create(const uint8_t* len, const uint8_t* exp, zs_dict** out) 
                             ll) != hipSuccess ||
         hipFuncSetAttribute((const void*)compress_kernel<16, kCapLarge>, hipFuncAttributeMaxDynamicSharedMemorySize,
                             ll) != hipSuccess ||
-        hipFuncSetAttribute((const void*)decompress_kernel<kPhaseEmit>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                            (int)decompress_lds().total) != hipSuccess ||
-        hipFuncSetAttribute((const void*)decompress_kernel<kPhaseLookback>,
-                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)decompress_lds().total) != hipSuccess) {
+        hipFuncSetAttribute((const void*)decompress_kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
+                            (int)decompress_lds().total) != hipSuccess) {
         (void)hipFree(d->d_tables);
         delete d;
         return ZS_EDEVICE;
@@ -2774,12 +2719,9 @@ static zs_status decompress_common(const zs_dict* d, const uint8_t* in, uint64_t
     uint32_t tl = kDL;
     while (tl > 32 && (nreq + tl - 1) / tl < want) tl >>= 1;
     const uint32_t ntiles = tiles_for(nreq, tl);
-    const bool small = ntiles <= kLookbackTiles;
     WsHeader* h = (WsHeader*)ws;
     uint64_t* status = (uint64_t*)(h + 1);
-    uint32_t* tile_total = (uint32_t*)((uint8_t*)status + align256((size_t)ntiles * 8));
-    uint64_t* tile_base = (uint64_t*)((uint8_t*)tile_total + align256((size_t)ntiles * 4));
-    if (launch_init(h, status, small ? ntiles : 0, (ResultOut*)res, s) != ZS_OK) return ZS_EDEVICE;
+    if (launch_init(h, status, ntiles, (ResultOut*)res, s) != ZS_OK) return ZS_EDEVICE;
     DecompressArgs a;
     a.tl = tl;
     a.tables = d->d_tables;
@@ -2795,35 +2737,16 @@ static zs_status decompress_common(const zs_dict* d, const uint8_t* in, uint64_t
     a.ntiles = ntiles;
     a.ws = h;
     a.status = status;
-    a.tile_total = tile_total;
-    a.tile_base = tile_base;
     a.res = (ResultOut*)res;
-    const DecompressLds dl = decompress_lds();
-    auto grid_for = [&](const void* kfn, uint32_t lds, int cap) {
-        int occ = 0;
-        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, kfn, kWG, lds) != hipSuccess || occ < 1)
-            occ = 1;
-        if (occ > cap) occ = cap;
-        uint32_t g = (uint32_t)di.cus * (uint32_t)occ;
-        return g > ntiles ? ntiles : g;
-    };
-    if (small) {
-        a.phase = kPhaseLookback;
-        hipLaunchKernelGGL(decompress_kernel<kPhaseLookback>,
-                           dim3(grid_for((const void*)decompress_kernel<kPhaseLookback>, dl.total, kDecompressWgPerCu)),
-                           dim3(kWG), dl.total, s, a);
-    } else {
-        a.phase = kPhaseSizes;
-        hipLaunchKernelGGL(decompress_kernel<kPhaseSizes>,
-                           dim3(grid_for((const void*)decompress_kernel<kPhaseSizes>, dl.total_sizes,
-                                         kDecompressSizesWgPerCu)),
-                           dim3(kWG), dl.total_sizes, s, a);
-        hipLaunchKernelGGL(tile_scan_kernel, dim3(1), dim3(kScanWG), 0, s, tile_total, tile_base, ntiles);
-        a.phase = kPhaseEmit;
-        hipLaunchKernelGGL(decompress_kernel<kPhaseEmit>,
-                           dim3(grid_for((const void*)decompress_kernel<kPhaseEmit>, dl.total, kDecompressWgPerCu)),
-                           dim3(kWG), dl.total, s, a);
-    }
+    const uint32_t lds = decompress_lds().total;
+    int occ = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, (const void*)decompress_kernel, kWG, lds) != hipSuccess ||
+        occ < 1)
+        occ = 1;
+    if (occ > kDecompressWgPerCu) occ = kDecompressWgPerCu;
+    uint32_t grid = (uint32_t)di.cus * (uint32_t)occ;
+    if (grid > ntiles) grid = ntiles;
+    hipLaunchKernelGGL(decompress_kernel, dim3(grid), dim3(kWG), lds, s, a);
     return hipGetLastError() == hipSuccess ? ZS_OK : ZS_EDEVICE;
 }
 
