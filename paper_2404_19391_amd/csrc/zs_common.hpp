@@ -295,11 +295,12 @@ struct StageWriter {
     }
 };
 
-// Copy a parked tile's total bytes from its global slot (16-byte aligned,
-// readable up to total + 16 bytes) to out[base, base + total) directly: each
-// thread loads the two slot chunks that one 16-byte chunk of the destination
+// Copy total bytes from a 16-byte aligned buffer (a tile parked in its global
+// slot, or a stage in LDS) to out[base, base + total) directly: each thread
+// loads the two source chunks that one 16-byte chunk of the destination
 // straddles, shifts them into place and stores 16 bytes (byte stores at the
-// two partial ends).
+// two partial ends).  No source chunk past the one holding byte total - 1 is
+// read.
 __device__ inline void copy_slot_direct(uint8_t* out, const uint8_t* slot, uint32_t total, uint64_t base) {
     const uintptr_t dst = (uintptr_t)(out + base);
     const uintptr_t a0 = dst & ~(uintptr_t)15;

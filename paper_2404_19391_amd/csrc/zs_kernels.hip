@@ -1456,6 +1456,44 @@ struct Decoder {
             if (t >= A.ntiles) break;
             bool regular;
             const uint32_t nl = setup_tile(t, &regular);
+            if (A.out) {
+                // the usual tile, one batch: lengths and bytes in one pass, the
+                // bytes at tile-relative stage positions; once the look-back has
+                // placed the tile they are copied out shifted to its alignment
+                uint32_t b1, lo, hi;
+                bool anybad, clean, err, spill;
+                load_batch(0, nl, regular, gather, &b1, &lo, &hi, &anybad, &clean);
+                if (b1 == nl) {
+                    uint32_t T = pass(0, nl, lo, hi, anybad, true, 0, &err, &spill, clean);
+                    if (err) {
+                        T = pass(0, nl, lo, hi, true, true, 0, &err, &spill, false);
+                        if (tid < nl && BAD()[tid] == kErrCorrupt) note_error(A.ws, r0 + tid, kErrCorrupt);
+                        anybad = true;
+                        clean = false;
+                    }
+                    if (tid < 64) {
+                        const uint64_t ex = lookback(A.status, t, T);
+                        if (tid == 0) ((uint64_t*)misc)[kDmBase64 / 2] = ex;
+                    }
+                    __syncthreads();
+                    const uint64_t gbase = ((uint64_t*)misc)[kDmBase64 / 2];
+                    if (t == 0 && tid == 0) A.out_off[0] = 0;
+                    write_offsets(0, nl, gbase);
+                    const bool fits = gbase + T <= A.out_cap;
+                    if (!fits && tid == 0) atomicOr(&A.ws->enospc, 1u);
+                    if (fits) {
+                        if (!spill) {
+                            copy_slot_direct(A.out, STAGE(), T, gbase);
+                        } else {  // more output than the stage holds: windows
+                            __syncthreads();
+                            decode_batch(0, nl, lo, hi, anybad, clean, gbase, true);
+                        }
+                    }
+                    __syncthreads();
+                    continue;
+                }
+                __syncthreads();
+            }
             uint32_t tpos = 0, b0 = 0, nb = 0, T = 0, lo = 0, hi = 0, lb1 = 0;
             bool lbad = false, lclean = false;
             while (b0 < nl) {
