@@ -1445,24 +1445,52 @@ struct Decoder {
     }
 
     // Tiles in ticket order, each placed by a decoupled look-back once its
-    // size is known.
+    // size is known.  A tile decoded in one pass publishes its size and keeps
+    // its bytes in the stage; it is placed one step later, after the next
+    // tile's framing and load, so that its predecessors have had time to
+    // publish and the workgroup does not wait on them.
     __device__ __forceinline__ void run_lookback() {
         uint32_t* misc = MISC();
         uint32_t* llen = LLEN();
         const uint32_t tid = threadIdx.x;
         const bool gather = A.ids != nullptr;
+        bool pend = false;
+        uint32_t pt = 0, pT = 0, pnl = 0;
+        uint64_t pr0 = 0;
+        // with at most one tile per workgroup nothing is gained by waiting
+        const bool defer = A.ntiles > gridDim.x;
+        // place the pending tile: its line ends are still in LLEN, its bytes in the stage
+        auto place_pending = [&]() {
+            if (tid < 64) {
+                const uint64_t ex = lookback_walk(A.status, pt, pT);
+                if (tid == 0) ((uint64_t*)misc)[kDmBase64 / 2] = ex;
+            }
+            __syncthreads();
+            const uint64_t gbase = ((uint64_t*)misc)[kDmBase64 / 2];
+            if (pt == 0 && tid == 0) A.out_off[0] = 0;
+            if (tid < pnl) A.out_off[pr0 + tid + 1] = gbase + llen[tid];
+            const bool fits = gbase + pT <= A.out_cap;
+            if (!fits && tid == 0) atomicOr(&A.ws->enospc, 1u);
+            if (fits) copy_slot_direct(A.out, STAGE(), pT, gbase);
+            __syncthreads();
+            pend = false;
+        };
         while (true) {
             const uint32_t t = claim_tile(A.ws, &misc[kDmSlot]);
-            if (t >= A.ntiles) break;
+            if (t >= A.ntiles) {
+                if (pend) place_pending();
+                break;
+            }
             bool regular;
             const uint32_t nl = setup_tile(t, &regular);
             if (A.out) {
                 // the usual tile, one batch: lengths and bytes in one pass, the
-                // bytes at tile-relative stage positions; once the look-back has
-                // placed the tile they are copied out shifted to its alignment
+                // bytes at tile-relative stage positions, copied out shifted to
+                // the tile's alignment once it is placed
                 uint32_t b1, lo, hi;
                 bool anybad, clean, err, spill;
                 load_batch(0, nl, regular, gather, &b1, &lo, &hi, &anybad, &clean);
+                if (pend) place_pending();
                 if (b1 == nl) {
                     uint32_t T = pass(0, nl, lo, hi, anybad, true, 0, &err, &spill, clean);
                     if (err) {
@@ -1471,6 +1499,16 @@ struct Decoder {
                         anybad = true;
                         clean = false;
                     }
+                    if (!spill && defer) {
+                        if (tid == 0) publish_aggregate(A.status, t, T);
+                        pend = true;
+                        pt = t;
+                        pT = T;
+                        pnl = nl;
+                        pr0 = r0;
+                        continue;
+                    }
+                    // placed at once; more output than the stage holds goes out in windows
                     if (tid < 64) {
                         const uint64_t ex = lookback(A.status, t, T);
                         if (tid == 0) ((uint64_t*)misc)[kDmBase64 / 2] = ex;
@@ -1484,7 +1522,7 @@ struct Decoder {
                     if (fits) {
                         if (!spill) {
                             copy_slot_direct(A.out, STAGE(), T, gbase);
-                        } else {  // more output than the stage holds: windows
+                        } else {
                             __syncthreads();
                             decode_batch(0, nl, lo, hi, anybad, clean, gbase, true);
                         }

@@ -236,7 +236,8 @@ def _random_compressed(odict, n_lines, seed, p_esc=0.08, p_bad=0.0):
 
 
 def test_decompress_many_tiles(zs, gd, odict):
-    """More tiles than one look-back launch takes: sizes, scan of the tile totals, emit."""
+    """More tiles than workgroups: each tile is placed one step after it is decoded
+    (deferred look-back), in bulk and in gather mode."""
     buf, off = _random_compressed(odict, 400000, 81)
     code, _ = _compare_decompress(zs, gd, odict, buf, off)
     assert code == oracle.OK
