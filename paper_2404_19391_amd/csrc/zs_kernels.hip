@@ -2033,8 +2033,7 @@ struct IndexArgs {
     uint64_t* n_lines_out;
     uint32_t ntiles;
     WsHeader* ws;
-    uint32_t* tile_total;       // newlines per tile (count phase)
-    const uint64_t* tile_base;  // exclusive prefix of tile_total (write phase)
+    uint64_t* status;  // look-back words, one per tile (newline counts)
     ResultOut* res;
 };
 
@@ -2058,33 +2057,6 @@ __device__ inline uint4 load16_or_pad(const uint8_t* buf, uint64_t len, uint64_t
     return make_uint4(w[0], w[1], w[2], w[3]);
 }
 
-// Count phase: newlines per tile.  Round k of a tile covers bytes
-// [4096 k, 4096 k + 4096), 16 per thread, so every load is coalesced.
-__global__ void __launch_bounds__(kWG) index_count_kernel(IndexArgs a) {
-    __shared__ uint32_t sc[kWaves];
-    const uint32_t tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
-    const bool aligned = (((uintptr_t)a.buf) & 15) == 0;
-    for (uint32_t t = blockIdx.x; t < a.ntiles; t += gridDim.x) {
-        const uint64_t tb = (uint64_t)t * kIdxTile;
-        uint32_t cnt = 0;
-#pragma unroll
-        for (int k = 0; k < kIdxRounds; k++) {
-            const uint4 v = load16_or_pad(a.buf, a.len, tb + 4096u * k + 16u * tid, aligned);
-            cnt += __popc(newline_bits(v.x)) + __popc(newline_bits(v.y)) + __popc(newline_bits(v.z)) +
-                   __popc(newline_bits(v.w));
-        }
-        const uint32_t s = (uint32_t)wave_sum64(cnt);
-        if (lane == 0) sc[w] = s;
-        __syncthreads();
-        if (tid == 0) {
-            uint32_t tot = 0;
-            for (int k = 0; k < kWaves; k++) tot += sc[k];
-            a.tile_total[t] = tot;
-        }
-        __syncthreads();
-    }
-}
-
 // The newline flags (bit 7 of each byte, from newline_bits) of a 4-byte word
 // as 4 bits: a multiply gathers bits 0, 8, 16, 24 at bits 21..24 (no two
 // partial products overlap).
@@ -2092,17 +2064,58 @@ __device__ inline uint32_t compact4(uint32_t nl) { return (((nl >> 7) * 0x002040
 
 constexpr int kIdxLdsCap = kIdxTile / 4;  // newline positions of a tile staged in LDS (u16 each)
 
-// Write phase: the same loads, one 16-bit newline mask per round in registers,
-// the eight round counts scanned together.  Each newline's tile-relative
-// position goes to LDS at its rank, then the tile's offsets are written as one
-// contiguous, coalesced run; a tile with more newlines than the LDS holds
-// writes them from the masks directly.
-__global__ void __launch_bounds__(kWG) index_write_kernel(IndexArgs a) {
+// One pass over the buffer.  Tiles are taken in ticket order; round k of a tile
+// covers bytes [4096 k, 4096 k + 4096), 16 per thread, so every load is
+// coalesced, and each round's newlines are kept as a 16-bit mask.  A tile
+// publishes its newline count for a decoupled look-back and ranks its newlines
+// into LDS (two buffers); it is placed one step later, after the next tile has
+// been read, and its offsets go out as one contiguous, coalesced run.  A tile
+// with more newlines than the LDS holds is placed at once and written from its
+// masks.
+__global__ void __launch_bounds__(kWG) index_kernel(IndexArgs a) {
     __shared__ uint32_t sc[kWaves][kIdxRounds];
-    __shared__ uint16_t pos[kIdxLdsCap];
+    __shared__ uint16_t pos[2][kIdxLdsCap];
+    __shared__ uint32_t slot;
+    __shared__ uint64_t sbase_sh;
     const uint32_t tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
     const bool aligned = (((uintptr_t)a.buf) & 15) == 0;
-    for (uint32_t t = blockIdx.x; t < a.ntiles; t += gridDim.x) {
+    bool pend = false;
+    uint32_t pt = 0, ptot = 0, pb = 0, cur = 0;
+    // after the last tile is placed: the virtual final newline, off[0], the count
+    auto finish_last = [&](uint64_t sbase, uint32_t tot) {
+        if (tid == 0) {
+            uint64_t lines = sbase + tot;
+            if (a.buf[a.len - 1] != '\n') {
+                lines++;
+                if (lines < a.off_cap) a.off[lines] = a.len + 1;
+            }
+            if (a.off_cap > 0) a.off[0] = 0;
+            *a.n_lines_out = lines;
+            if (lines + 1 > a.off_cap) atomicOr(&a.ws->enospc, 1u);
+        }
+    };
+    auto place_pending = [&]() {
+        if (tid < 64) {
+            const uint64_t ex = lookback_walk(a.status, pt, ptot);
+            if (tid == 0) sbase_sh = ex;
+        }
+        __syncthreads();
+        const uint64_t sbase = sbase_sh;
+        const uint64_t tb = (uint64_t)pt * kIdxTile;
+        for (uint32_t i = tid; i < ptot; i += kWG) {
+            const uint64_t k1 = sbase + 1 + i;
+            if (k1 < a.off_cap) a.off[k1] = tb + pos[pb][i];
+        }
+        if (pt + 1 == a.ntiles) finish_last(sbase, ptot);
+        pend = false;
+        __syncthreads();  // sbase_sh is read by every wave before it is written again
+    };
+    while (true) {
+        const uint32_t t = claim_tile(a.ws, &slot);
+        if (t >= a.ntiles) {
+            if (pend) place_pending();
+            break;
+        }
         const uint64_t tb = (uint64_t)t * kIdxTile;
         uint32_t m16[kIdxRounds], ex[kIdxRounds];
         uint4 v[kIdxRounds];
@@ -2134,27 +2147,37 @@ __global__ void __launch_bounds__(kWG) index_write_kernel(IndexArgs a) {
             uint32_t before = 0, round = 0;
 #pragma unroll
             for (int ww = 0; ww < kWaves; ww++) {
-                const uint32_t v = sc[ww][k];
-                before += ((uint32_t)ww < w) ? v : 0u;
-                round += v;
+                const uint32_t vv = sc[ww][k];
+                before += ((uint32_t)ww < w) ? vv : 0u;
+                round += vv;
             }
             ex[k] += tot + before;  // newlines of the tile before this thread's bytes of round k
             tot += round;
         }
-        const uint64_t sbase = a.tile_base[t];
-        if (tot <= (uint32_t)kIdxLdsCap) {
+        if (tid == 0) publish_aggregate(a.status, t, tot);
+        const bool staged = tot <= (uint32_t)kIdxLdsCap;
+        if (staged) {
 #pragma unroll
             for (int k = 0; k < kIdxRounds; k++) {
                 uint32_t j = ex[k];
                 const uint32_t p0 = 4096u * k + 16u * tid + 1u;  // tile offset just past byte 0 of the piece
-                for (uint32_t m = m16[k]; m; m &= m - 1) pos[j++] = (uint16_t)(p0 + (uint32_t)__builtin_ctz(m));
+                for (uint32_t m = m16[k]; m; m &= m - 1) pos[cur][j++] = (uint16_t)(p0 + (uint32_t)__builtin_ctz(m));
+            }
+        }
+        if (pend) place_pending();
+        if (staged) {
+            pend = true;
+            pt = t;
+            ptot = tot;
+            pb = cur;
+            cur ^= 1u;
+        } else {
+            if (tid < 64) {
+                const uint64_t e = lookback_walk(a.status, t, tot);
+                if (tid == 0) sbase_sh = e;
             }
             __syncthreads();
-            for (uint32_t i = tid; i < tot; i += kWG) {
-                const uint64_t k1 = sbase + 1 + i;
-                if (k1 < a.off_cap) a.off[k1] = tb + pos[i];
-            }
-        } else {
+            const uint64_t sbase = sbase_sh;
 #pragma unroll
             for (int k = 0; k < kIdxRounds; k++) {
                 uint64_t k1 = sbase + ex[k];
@@ -2164,16 +2187,7 @@ __global__ void __launch_bounds__(kWG) index_write_kernel(IndexArgs a) {
                     if (k1 < a.off_cap) a.off[k1] = x + (uint32_t)__builtin_ctz(m);
                 }
             }
-        }
-        if (t + 1 == a.ntiles && tid == 0) {
-            uint64_t lines = sbase + tot;
-            if (a.len > 0 && a.buf[a.len - 1] != '\n') {
-                lines++;
-                if (lines < a.off_cap) a.off[lines] = a.len + 1;
-            }
-            if (a.off_cap > 0) a.off[0] = 0;
-            *a.n_lines_out = lines;
-            if (lines + 1 > a.off_cap) atomicOr(&a.ws->enospc, 1u);
+            if (t + 1 == a.ntiles) finish_last(sbase, tot);
         }
         __syncthreads();
     }
@@ -2274,7 +2288,7 @@ size_t ws_bytes_for(int op, uint64_t n) {
         }
         case ZS_OP_INDEX: {
             const size_t nt = tiles_for(n, kIdxTile);
-            return h + align256(nt * 4) + (nt + 1) * 8;
+            return h + align256(nt * 8);
         }
         default:
             return 0;
@@ -2855,9 +2869,8 @@ zs_status zs_index_lines(const uint8_t* buf, uint64_t len, uint64_t* off, uint64
     if (!di.ok) return ZS_EDEVICE;
     const uint32_t ntiles = tiles_for(len, kIdxTile);
     WsHeader* h = (WsHeader*)ws;
-    uint32_t* tile_total = (uint32_t*)(h + 1);
-    uint64_t* tile_base = (uint64_t*)((uint8_t*)tile_total + align256((size_t)ntiles * 4));
-    if (launch_init(h, nullptr, 0, (ResultOut*)res, s) != ZS_OK) return ZS_EDEVICE;
+    uint64_t* status = (uint64_t*)(h + 1);
+    if (launch_init(h, status, ntiles, (ResultOut*)res, s) != ZS_OK) return ZS_EDEVICE;
     IndexArgs a;
     a.buf = buf;
     a.len = len;
@@ -2866,14 +2879,15 @@ zs_status zs_index_lines(const uint8_t* buf, uint64_t len, uint64_t* off, uint64
     a.n_lines_out = n_lines_out;
     a.ntiles = ntiles;
     a.ws = h;
-    a.tile_total = tile_total;
-    a.tile_base = tile_base;
+    a.status = status;
     a.res = (ResultOut*)res;
-    uint32_t grid = (uint32_t)di.cus * kIndexWgPerCu;
+    int occ = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, (const void*)index_kernel, kWG, 0) != hipSuccess || occ < 1)
+        occ = 1;
+    if (occ > kIndexWgPerCu) occ = kIndexWgPerCu;
+    uint32_t grid = (uint32_t)di.cus * (uint32_t)occ;
     if (grid > ntiles) grid = ntiles;
-    hipLaunchKernelGGL(index_count_kernel, dim3(grid), dim3(kWG), 0, s, a);
-    hipLaunchKernelGGL(tile_scan_kernel, dim3(1), dim3(kScanWG), 0, s, tile_total, tile_base, ntiles);
-    hipLaunchKernelGGL(index_write_kernel, dim3(grid), dim3(kWG), 0, s, a);
+    hipLaunchKernelGGL(index_kernel, dim3(grid), dim3(kWG), 0, s, a);
     return hipGetLastError() == hipSuccess ? ZS_OK : ZS_EDEVICE;
 }
 

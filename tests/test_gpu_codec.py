@@ -283,6 +283,14 @@ def test_index_lines(zs, odict):
     buf, off = smilesgen.generate("uneven", 72, 100000)
     got = zs.index_lines(torch.from_numpy(buf).cuda())
     assert np.array_equal(host(got).astype(np.uint64), off)
+    # more 32 KiB tiles than workgroups (tiles wait for their placement while the
+    # next one is read), and runs of empty lines denser than the LDS staging
+    # holds (those tiles are placed at once), without a final newline
+    big, _ = smilesgen.generate("bulk", 74, 900000)
+    nl = np.full(100000, ord("\n"), dtype=np.uint8)
+    data = np.concatenate([big[:20_000_000], nl, big[20_000_000:], nl, np.frombuffer(b"CCO", dtype=np.uint8)])
+    got = zs.index_lines(torch.from_numpy(data).cuda())
+    assert np.array_equal(host(got).astype(np.uint64), oracle.index_lines(data))
 
 
 def test_determinism(zs, gd, odict):
