@@ -37,13 +37,16 @@ __device__ inline void note_error(WsHeader* h, uint64_t index, uint32_t kind) {
 constexpr uint64_t kFlagAgg = 1ull << 62, kFlagInc = 2ull << 62, kValMask = (1ull << 62) - 1;
 
 // The words carry sizes only: no workgroup reads data another one wrote, so
-// relaxed device-scope atomics suffice.  (Acquire/release at device scope
-// would write back and invalidate the XCD's L2 at every access.)
+// no acquire/release ordering is needed (at device scope it would write back
+// and invalidate the XCD's L2 at every access).  The words themselves are read
+// and written with read-modify-write atomics, which are performed at the
+// device's coherence point: a plain load, even a device-scope one, may be
+// served from a copy in the reading XCD's own L2 and miss another XCD's update.
 __device__ inline void status_store(uint64_t* p, uint64_t v) {
-    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    (void)__hip_atomic_exchange(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 __device__ inline uint64_t status_load(uint64_t* p) {
-    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    return __hip_atomic_fetch_add(p, (uint64_t)0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
 __device__ inline uint64_t wave_sum64(uint64_t v) {

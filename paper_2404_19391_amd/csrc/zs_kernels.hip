@@ -939,15 +939,26 @@ struct Compressor {
                 const uint64_t pbase = ((uint64_t*)misc)[6];
                 if (tid < pnl) A.out_off[pk0 + tid + 1] = pbase + prel;
                 if (A.out) {
-                    if (pbase + ptotal <= A.out_cap) copy_slot_direct(A.out, slot, ptotal, pbase);
-                    else if (tid == 0) atomicOr(&A.ws->enospc, 1u);
+                    if (pbase + ptotal <= A.out_cap) {
+                        // each thread reads back only the slot chunks it wrote (a global
+                        // store of another wave need not be visible after a barrier),
+                        // into the free LDS buffer; the shifted copy then reads LDS
+                        for (uint32_t c = tid; c < (ptotal + 15) / 16; c += kWG)
+                            ((uint4*)stage)[c] = ((const uint4*)slot)[c];
+                        __syncthreads();
+                        copy_slot_direct(A.out, stage, ptotal, pbase);
+                    } else if (tid == 0) {
+                        atomicOr(&A.ws->enospc, 1u);
+                    }
                 }
                 pend = false;
                 __syncthreads();
             }
             if (!have) break;
             if (t == 0 && tid == 0) A.out_off[0] = 0;
-            const bool defer = nb == 1 && total + 16 <= (uint32_t)kSlotBytes;
+            // Binned (gather) launches place every tile at once: parked tiles gave
+            // wrong bytes there under load, a cause not yet found.
+            const bool defer = nb == 1 && total + 16 <= (uint32_t)kSlotBytes && A.ids == nullptr;
             if (defer) {
                 prel = e + mylen;  // this line's end inside the tile, until the tile is placed
                 if (A.out) {

@@ -77,6 +77,29 @@ def test_binned_many_tiles(zs, gd, odict):
     _check(zs, gd, odict, *smilesgen.generate("uneven", 96, 60000), cfgs=CONFIGS[1:3])
 
 
+def test_binned_repeated_calls_agree(zs, gd, odict):
+    """300,000 uneven lines (thousands of tiles, long-line bins that take several
+    batches) compressed ten times in a row with one workspace: every call gives the
+    plain compressor's bytes and offsets (a regression test for tiles placed with
+    stale bytes under load)."""
+    buf, off = smilesgen.generate("uneven", 97, 300000)
+    b, o = dev(buf, off)
+    want, woff = zs.compress(gd, b, o)
+    cfg = zs.BinConfig.make(edges=(128,), lines_per_tile=(256, 256), large_lds=(0, 0))
+    total = int(host(woff)[-1])
+    ws = torch.empty(zs.binned_workspace_bytes(300000, total), dtype=torch.uint8, device="cuda")
+    out = torch.empty(total + 16, dtype=torch.uint8, device="cuda")
+    ooff = torch.empty(300001, dtype=torch.int64, device="cuda")
+    res = zs.new_result()
+    for _ in range(10):
+        out.fill_(0)
+        zs.compress_binned_into(gd, b, o, out, ooff, cfg, ws, res)
+        torch.cuda.synchronize()
+        assert zs.read_result(res)[0] == 0
+        assert torch.equal(ooff, woff)
+        assert torch.equal(out[:total], want)
+
+
 def test_binned_errors_and_sizes(zs, gd, odict):
     lines = [b"CCO", b"C\tC", b"c1ccccc1", b"N\x7f", b"C" * 4097, b"CC"] * 50 + [b"C" * 900, b"\xff"]
     buf, off = oracle.join_lines(lines)
