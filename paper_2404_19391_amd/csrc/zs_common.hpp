@@ -335,25 +335,4 @@ __device__ inline void copy_slot_direct(uint8_t* out, const uint8_t* slot, uint3
     }
 }
 
-// Copy a deferred tile's bytes from its global slot to out[base, base+total),
-// through an LDS stage shifted to the destination's 16-byte alignment.  The
-// stage must hold total + 15 bytes.
-__device__ inline void copy_slot_out(uint8_t* out, const uint8_t* slot, uint32_t total, uint64_t base,
-                                     uint8_t* stage) {
-    const uintptr_t dst = (uintptr_t)(out + base);
-    const uint32_t shift = (uint32_t)(dst & 15);
-    const uint32_t nch = (total + 15) / 16;
-    for (uint32_t c = threadIdx.x; c < nch; c += kWG) {
-        const uint4 v = *(const uint4*)(slot + 16 * c);
-        const uint32_t w[4] = {v.x, v.y, v.z, v.w};
-#pragma unroll
-        for (int k = 0; k < 16; k++) {
-            if (16 * c + k < total) stage[shift + 16 * c + k] = (uint8_t)(w[k >> 2] >> (8 * (k & 3)));
-        }
-    }
-    __syncthreads();
-    flush_stage(out, base, base + total, dst - shift, stage);
-    __syncthreads();
-}
-
 }  // namespace zs
