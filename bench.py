@@ -30,6 +30,9 @@ if ROOT not in sys.path:
 
 METRIC = "compress & decompress GB/s on 1 MI355X (frac of HBM peak); p99 random-access latency"
 HBM_PEAK_GBS = 8000.0
+# wave64 VALU instructions issued per second: 256 CUs x 4 SIMDs, one wave-instruction per
+# 4 cycles each (64 lanes on 16-wide SIMDs), at 2.4 GHz
+VALU_ISSUE_PEAK = 256 * 4 * 2.4e9 / 4
 
 
 def parse():
@@ -111,19 +114,36 @@ def kernel_source_hash():
     return h.hexdigest()
 
 
-def measured_traffic(kernel):
-    """HBM bytes per launch of `kernel` from the committed counter summary, if it was taken
-    from the kernel sources as they are now; else None."""
+def measured_counters(kernel):
+    """The committed counter summary of `kernel` (HBM bytes, VALU instructions and LDS bank
+    conflicts per launch), if it was taken from the kernel sources as they are now; else {}."""
     path = os.path.join(ROOT, "profiles", "traffic.json")
     try:
         with open(path) as f:
             t = json.load(f)
     except (OSError, ValueError):
-        return None
+        return {}
     e = t.get(kernel)
     if not e or e.get("source_sha256") != kernel_source_hash():
-        return None
-    return e.get("bytes_per_launch")
+        return {}
+    return e
+
+
+def measured_traffic(kernel):
+    """HBM bytes per launch of `kernel` from the committed counter summary, or None."""
+    return measured_counters(kernel).get("bytes_per_launch")
+
+
+def copy_peak_gbs(dev, stream, reps=6):
+    """Best device-to-device copy rate (GB/s, read + write bytes) of a 1 GiB buffer on this
+    GPU: the measured HBM ceiling beside the published one."""
+    import torch
+    src = torch.empty(1 << 30, dtype=torch.uint8, device=dev)
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    t = time_ms(lambda: dst.copy_(src), stream, reps)
+    del src, dst
+    return 2.0 * (1 << 30) / (min(t) * 1e-3) / 1e9
 
 
 def time_ms(fn, stream, reps):
@@ -571,6 +591,17 @@ def main():
             "achieved": round(comp_hbm, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": round(comp_hbm / HBM_PEAK_GBS, 4), "traffic": measured_traffic("compress_kernel"),
             "alg_bytes_per_launch": comp_alg, "avg_launch_ms": round(mean["compress"], 4)}
+    # the roof the kernel actually meets: VALU instruction issue (counters of the same sources,
+    # divided by the live launch time), and the HBM fraction against a measured copy as well
+    ctr = measured_counters("compress_kernel")
+    if ctr.get("valu_insts_per_launch"):
+        rate = ctr["valu_insts_per_launch"] / (mean["compress"] * 1e-3)
+        roof["valu_issue"] = {"achieved_G_per_s": round(rate / 1e9, 1), "peak_G_per_s": VALU_ISSUE_PEAK / 1e9,
+                              "frac": round(rate / VALU_ISSUE_PEAK, 4),
+                              "lds_bank_conflict_frac": ctr.get("lds_bank_conflict_frac")}
+    cp = copy_peak_gbs(dev, stream)
+    roof["copy_peak_measured_GBs"] = round(cp, 1)
+    roof["frac_of_measured_copy"] = round(comp_hbm / cp, 4)
     if args.probe_copy:
         # a plain copy of known size, for the counter scale factor of the HBM byte counters
         src = torch.empty(1 << 30, dtype=torch.uint8, device=dev)

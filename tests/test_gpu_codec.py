@@ -289,8 +289,23 @@ def test_index_lines(zs, odict):
     big, _ = smilesgen.generate("bulk", 74, 900000)
     nl = np.full(100000, ord("\n"), dtype=np.uint8)
     data = np.concatenate([big[:20_000_000], nl, big[20_000_000:], nl, np.frombuffer(b"CCO", dtype=np.uint8)])
-    got = zs.index_lines(torch.from_numpy(data).cuda())
-    assert np.array_equal(host(got).astype(np.uint64), oracle.index_lines(data))
+    db = torch.from_numpy(data).cuda()
+    want = oracle.index_lines(data)
+    got = zs.index_lines(db)
+    assert np.array_equal(host(got).astype(np.uint64), want)
+    # an offsets array that is too short: the entries that fit, the full line
+    # count, and ZS_ENOSPC; nothing written past off_cap
+    ws = zs.Workspaces().get(zs.OP_INDEX, db.numel())
+    for cap in (0, 1, 5000, len(want) - 1, len(want)):
+        o = torch.full((cap + 64,), -1, dtype=torch.int64, device="cuda")
+        n_out = torch.zeros(1, dtype=torch.int64, device="cuda")
+        res = zs.new_result()
+        zs.index_into(db, o[:cap], n_out, ws, res)
+        assert zs.read_result(res)[0] == (zs.ENOSPC if cap < len(want) else 0)
+        assert int(n_out.item()) == len(want) - 1
+        h = host(o)
+        assert np.array_equal(h[:cap].astype(np.uint64), want[:cap])
+        assert (h[cap:] == -1).all()
 
 
 def test_determinism(zs, gd, odict):
