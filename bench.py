@@ -46,9 +46,10 @@ def parse():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--cpu-lines", type=int, default=800_000)
     ap.add_argument("--only", default="", help="comma list of ops to run (profiling runs)")
-    ap.add_argument("--workload", default="bulk", choices=["bulk", "uneven", "serve"],
+    ap.add_argument("--workload", default="bulk", choices=["bulk", "uneven", "serve", "random"],
                     help="bulk: the headline step; uneven: plain vs length-binned / autotuned / graph "
-                         "compression; serve: the request loop under Poisson arrivals")
+                         "compression; serve: the request loop under Poisson arrivals; random: random-access "
+                         "batches on a resident 40M-line shard")
     ap.add_argument("--serve-requests", type=int, default=10000)
     ap.add_argument("--serve-gb", type=float, default=50.0, help="compressed shard bytes resident (GB)")
     ap.add_argument("--shard-lines", type=int, default=40_000_000)
@@ -435,6 +436,133 @@ def bench_serve(args):
     print(json.dumps(out), flush=True)
 
 
+def bench_random(args):
+    """Random access on a resident shard: 40M lines of the bulk distribution, compressed on
+    the device and kept with its uint64 index; batches of 1k, 10k and 100k distinct uniform
+    ids (10% of the 1k batches are one contiguous range instead), decompressed and packed in
+    request order. Latency per batch is enqueue -> completion with the ids already on the
+    device, and again with the ids copied from pinned host memory inside the bracket. Every
+    20th batch is compared with the same lines cut out of a bulk decompression of the shard."""
+    import torch
+    import paper_2404_19391_amd as zs
+    import smilesgen
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    n = args.shard_lines
+    nb = args.ra_batches if args.ra_batches != 200 else 1000
+    log("generating the %d-line shard" % n)
+    buf, off = smilesgen.generate("bulk", 4, n, threads=16)
+    raw = int(buf.size)
+    d = zs.Dict.load()
+    b = torch.from_numpy(buf).to(dev)
+    o = torch.from_numpy(off.astype(np.int64)).to(dev)
+    del buf, off
+    c, c_off = zs.compress(d, b, o)
+    r, r_off = zs.decompress(d, c, c_off)
+    del b, o
+    torch.cuda.synchronize()
+    cbytes = int(c.numel())
+    c_len = (c_off[1:] - c_off[:-1]).cpu().numpy()
+    r_len = (r_off[1:] - r_off[:-1]).cpu().numpy()
+    log("shard: %d lines, %d raw -> %d compressed bytes" % (n, raw, cbytes))
+    stream = torch.cuda.current_stream()
+    kmax = 100_000
+    ws = zs.Workspaces(dev).get(zs.OP_DECOMPRESS_LINES, kmax)
+    res = zs.new_result(dev)
+    out = torch.empty(kmax * 256, dtype=torch.uint8, device=dev)
+    out_off = torch.empty(kmax + 1, dtype=torch.int64, device=dev)
+    ids_pin = torch.empty(kmax, dtype=torch.int64, pin_memory=True)
+    ids_dev = torch.empty(kmax, dtype=torch.int64, device=dev)
+    rng = np.random.default_rng(44)
+    per = {}
+    checked = bad = 0
+    for k in (1000, 10000, 100000):
+        log("random access: %d batches of %d ids" % (nb, k))
+        lat, lat_h2d, obytes, abytes, contiguous = [], [], [], [], 0
+        for it in range(nb + 3):
+            if k == 1000 and rng.random() < 0.1:
+                start = int(rng.integers(0, n - k))
+                ids_h = np.arange(start, start + k, dtype=np.int64)
+                contiguous += it >= 3
+            else:
+                ids_h = rng.choice(n, k, replace=False).astype(np.int64)
+            ids_pin[:k].copy_(torch.from_numpy(ids_h))
+            ids = ids_dev[:k]
+            ids.copy_(ids_pin[:k])
+            torch.cuda.synchronize()
+            e0, e1, e2 = (torch.cuda.Event(enable_timing=True) for _ in range(3))
+            e0.record(stream)
+            zs.decompress_lines_into(d, c, c_off, ids, out, out_off[:k + 1], ws, res)
+            e1.record(stream)
+            e1.synchronize()
+            # the same batch with the ids uploaded inside the bracket
+            e2.record(stream)
+            ids.copy_(ids_pin[:k], non_blocking=True)
+            zs.decompress_lines_into(d, c, c_off, ids, out, out_off[:k + 1], ws, res)
+            e3 = torch.cuda.Event(enable_timing=True)
+            e3.record(stream)
+            e3.synchronize()
+            code, fb = zs.read_result(res)
+            if code != 0:
+                raise SystemExit("random access failed: code %d first_bad %d" % (code, fb))
+            if it < 3:
+                continue
+            lat.append(e0.elapsed_time(e1) * 1e3)
+            lat_h2d.append(e2.elapsed_time(e3) * 1e3)
+            ob = int(r_len[ids_h].sum())
+            obytes.append(ob)
+            abytes.append(8 * k + 16 * k + int(c_len[ids_h].sum()) + ob + 8 * (k + 1))
+            if it % 20 == 0:
+                idt = torch.from_numpy(ids_h).to(dev)
+                st = r_off[idt]
+                ln = r_off[idt + 1] - st
+                cum = torch.cumsum(ln, 0)
+                pos = torch.repeat_interleave(st - (cum - ln), ln) + torch.arange(int(cum[-1]), device=dev)
+                ok = bool(torch.equal(out[:int(cum[-1])], r[pos]) and int(out_off[0]) == 0
+                          and torch.equal(out_off[1:k + 1], cum))
+                checked += 1
+                bad += not ok
+        lat = np.array(lat)
+        lat_h2d = np.array(lat_h2d)
+        med = float(np.median(lat))
+        per[str(k)] = {"batches": len(lat), "contiguous_batches": contiguous,
+                       "p50_us": round(float(np.percentile(lat, 50)), 2),
+                       "p99_us": round(float(np.percentile(lat, 99)), 2),
+                       "p50_us_with_id_upload": round(float(np.percentile(lat_h2d, 50)), 2),
+                       "p99_us_with_id_upload": round(float(np.percentile(lat_h2d, 99)), 2),
+                       "lines_per_s": round(k / (med * 1e-6), 1),
+                       "output_GBs": round(float(np.median(np.array(obytes) / (lat * 1e-6))) / 1e9, 2),
+                       "alg_GBs": round(float(np.median(np.array(abytes) / (lat * 1e-6))) / 1e9, 2)}
+    big = per["100000"]
+    res_line = {
+        "metric": METRIC,
+        "value": big["output_GBs"],
+        "unit": "GB/s",
+        "n_gpus": 1,
+        "steps": nb,
+        "warmup": 3,
+        "ms_per_step": round(big["p50_us"] * 1e-3, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "u8",
+        "data": "synthetic",
+        "config": {"workload": "random access: a %d-line shard of the bulk distribution (%.2f GB raw, %.2f GB "
+                               "compressed + %.2f GB index resident), batches of 1k/10k/100k distinct uniform ids, "
+                               "10%% of the 1k batches one contiguous range; value = output GB/s of the 100k "
+                               "batches (median)" % (n, raw / 1e9, cbytes / 1e9, 8 * (n + 1) / 1e9),
+                   "lines": n, "raw_bytes": raw, "compressed_bytes": cbytes},
+        "roofline": {"kernel": "decompress_kernel (gather, 100k ids)", "bound": "hbm",
+                     "achieved": big["alg_GBs"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": round(big["alg_GBs"] / HBM_PEAK_GBS, 4), "traffic": None},
+        "random_access": per,
+        "p99_random_access_us_100k": big["p99_us"],
+        "verified": {"batches_checked": checked, "mismatches": bad,
+                     "against": "the same lines cut from a bulk decompression of the shard"},
+    }
+    print(json.dumps(res_line), flush=True)
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -452,6 +580,8 @@ def main():
         return bench_uneven(args)
     if args.workload == "serve":
         return bench_serve(args)
+    if args.workload == "random":
+        return bench_random(args)
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
     only = set(args.only.split(",")) if args.only else {"index", "compress", "decompress", "random"}
