@@ -25,9 +25,11 @@
 #include <string.h>
 
 #include <algorithm>
+#include <map>
 #include <mutex>
 #include <new>
 #include <stddef.h>
+#include <tuple>
 #include <vector>
 
 #include "../../include/zsmiles.h"
@@ -1051,6 +1053,7 @@ __host__ __device__ inline DecompressLds decompress_lds() {
 
 struct DecompressArgs {
     const uint8_t* tables;
+    uint32_t off_len, off_exp;  // offsets of LEN and EXP in the table blob
     const uint8_t* in;
     uint64_t in_bytes;
     const uint64_t* in_off;
@@ -1470,6 +1473,9 @@ struct Decoder {
         uint64_t pr0 = 0;
         // with at most one tile per workgroup nothing is gained by waiting
         const bool defer = A.ntiles > gridDim.x;
+        // the first ticket was claimed in the kernel's prologue
+        uint32_t next = misc[kDmSlot];
+        bool claimed = true;
         // place the pending tile: its line ends are still in LLEN, its bytes in the stage
         auto place_pending = [&]() {
             if (tid < 64) {
@@ -1487,7 +1493,8 @@ struct Decoder {
             pend = false;
         };
         while (true) {
-            const uint32_t t = claim_tile(A.ws, &misc[kDmSlot]);
+            const uint32_t t = claimed ? next : claim_tile(A.ws, &misc[kDmSlot]);
+            claimed = false;
             if (t >= A.ntiles) {
                 if (pend) place_pending();
                 break;
@@ -1711,19 +1718,22 @@ struct Decoder {
 __global__ void __launch_bounds__(kWG) decompress_kernel(DecompressArgs a) {
     extern __shared__ __align__(16) uint8_t smem[];
     {
+        // the first tile's ticket is claimed while the tables load (the two
+        // round trips overlap); it waits in the decoder's slot word
+        uint32_t first = 0;
+        if (threadIdx.x == 0) first = atomicAdd(&a.ws->ticket, 1u);
         // header + LEN at [0, 320), EXP at [320, 320 + 4096), in 16-byte pieces
-        const TableHeader* h = (const TableHeader*)a.tables;
-        const uint32_t off_len = h->off_len, off_exp = h->off_exp;
         uint4* dst = (uint4*)smem;
         for (uint32_t k = threadIdx.x; k < (64 + 256 + 256 * kExpStride) / 16; k += kWG) {
             uint32_t src;
             if (k < 4) src = 16 * k;
-            else if (k < 20) src = off_len + 16 * (k - 4);
-            else src = off_exp + 16 * (k - 20);
+            else if (k < 20) src = a.off_len + 16 * (k - 4);
+            else src = a.off_exp + 16 * (k - 20);
             // the row of byte '\n' (never a code) holds a newline, for the
             // decoder's byte-parallel path
             dst[k] = (k == 20 + '\n') ? make_uint4('\n', 0, 0, 0) : *(const uint4*)(a.tables + src);
         }
+        if (threadIdx.x == 0) ((uint32_t*)(smem + decompress_lds().misc))[kDmSlot] = first;
     }
     __syncthreads();
     Decoder d(a, smem);
@@ -2268,6 +2278,23 @@ DeviceInfo device_info() {
     return cache[dev];
 }
 
+// Workgroups of kernel fn (256 threads, lds bytes of dynamic LDS) that fit one CU on
+// the current device, at least 1; asked of the runtime once per device and kernel.
+int occupancy(const void* fn, uint32_t lds) {
+    static std::mutex mu;
+    static std::map<std::tuple<int, const void*, uint32_t>, int> cache;
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return 1;
+    const auto key = std::make_tuple(dev, fn, lds);
+    std::lock_guard<std::mutex> g(mu);
+    auto it = cache.find(key);
+    if (it != cache.end()) return it->second;
+    int occ = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, fn, kWG, lds) != hipSuccess || occ < 1) occ = 1;
+    cache.emplace(key, occ);
+    return occ;
+}
+
 constexpr int kCompressWgPerCu = 4;  // upper bound of the persistent grid per CU (sizes the workspace)
 constexpr int kDecompressWgPerCu = 4;  // upper bound of the persistent decompression grid per CU
 constexpr int kIndexWgPerCu = 8;
@@ -2362,6 +2389,7 @@ BinnedWs binned_ws(void* ws, uint64_t n, uint64_t out_cap, int cus) {
 struct zs_dict {
     uint8_t* d_tables = nullptr;
     uint32_t blob_bytes = 0;
+    uint32_t off_len = 0, off_exp = 0;  // LEN and EXP in the blob (the decoder stages them)
     uint32_t comp_bytes = 0;  // prefix staged by the compressor
     uint32_t lmax = 0;
     uint32_t lk = 8;
@@ -2392,6 +2420,8 @@ zs_status zs_dict_create(const uint8_t* len, const uint8_t* exp, zs_dict** out) 
     if (!d) return ZS_ENOMEM;
     d->blob_bytes = h->blob_bytes;
     d->comp_bytes = h->off_exp;
+    d->off_len = h->off_len;
+    d->off_exp = h->off_exp;
     d->lmax = h->lmax;
     d->lk = h->lk;
     if (hipGetDevice(&d->device) != hipSuccess) {
@@ -2475,8 +2505,7 @@ static zs_status launch_compress(const zs_dict* d, const CompressArgs& a, bool l
                                                 : (const void*)compress_kernel<16, kCapGather>)
                                           : (k8 ? (const void*)compress_kernel<8, kCapSmall>
                                                 : (const void*)compress_kernel<16, kCapSmall>);
-    int occ = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, kfn, kWG, lds) != hipSuccess || occ < 1) occ = 1;
+    int occ = occupancy(kfn, lds);
     if (occ > kCompressWgPerCu) occ = kCompressWgPerCu;
     uint32_t grid = (uint32_t)cus * (uint32_t)occ;
     if (grid > max_tiles) grid = max_tiles;
@@ -2826,6 +2855,8 @@ static zs_status decompress_common(const zs_dict* d, const uint8_t* in, uint64_t
     DecompressArgs a;
     a.tl = tl;
     a.tables = d->d_tables;
+    a.off_len = d->off_len;
+    a.off_exp = d->off_exp;
     a.in = in;
     a.in_bytes = in_bytes;
     a.in_off = in_off;
@@ -2840,10 +2871,7 @@ static zs_status decompress_common(const zs_dict* d, const uint8_t* in, uint64_t
     a.status = status;
     a.res = (ResultOut*)res;
     const uint32_t lds = decompress_lds().total;
-    int occ = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, (const void*)decompress_kernel, kWG, lds) != hipSuccess ||
-        occ < 1)
-        occ = 1;
+    int occ = occupancy((const void*)decompress_kernel, lds);
     if (occ > kDecompressWgPerCu) occ = kDecompressWgPerCu;
     uint32_t grid = (uint32_t)di.cus * (uint32_t)occ;
     if (grid > ntiles) grid = ntiles;
@@ -2892,9 +2920,7 @@ zs_status zs_index_lines(const uint8_t* buf, uint64_t len, uint64_t* off, uint64
     a.ws = h;
     a.status = status;
     a.res = (ResultOut*)res;
-    int occ = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, (const void*)index_kernel, kWG, 0) != hipSuccess || occ < 1)
-        occ = 1;
+    int occ = occupancy((const void*)index_kernel, 0);
     if (occ > kIndexWgPerCu) occ = kIndexWgPerCu;
     uint32_t grid = (uint32_t)di.cus * (uint32_t)occ;
     if (grid > ntiles) grid = ntiles;
