@@ -1646,9 +1646,13 @@ struct Decoder {
             __syncthreads();
         } else {
             // gather: each thread fills 16-byte chunks of CB; the line of a
-            // chunk's first byte comes from a search of qoff, the 16 source
-            // loads are independent so they are all in flight together
+            // chunk's first byte comes from a search of qoff.  The source
+            // addresses are found first (LDS only), then the 16 loads are
+            // issued with no branch between them, so that they are all in
+            // flight together (a load inside the per-byte branches was waited
+            // for before the next one was issued)
             const uint32_t lo = qoff[b0], hi = qoff[b1];
+            const bool has_in = A.in_bytes > 0;
             for (uint32_t x0 = (lo & ~15u) + tid * 16; x0 < hi; x0 += kWG * 16) {
                 uint32_t l = b0, r = b1;
                 const uint32_t xs = max(x0, lo);
@@ -1659,11 +1663,13 @@ struct Decoder {
                 }
                 uint32_t qq = l;
                 uint32_t nb = qoff[qq + 1];
-                uint8_t v[16];
+                // per byte: kind (2 bits: 0 a byte of line qq at offset o, 1 a
+                // newline, 2 zero) | qq << 2 (qq <= kDL) | o << 11 (o <= kMaxCLine)
+                uint32_t pk[16];
 #pragma unroll
                 for (int k = 0; k < 16; k++) {
                     const uint32_t x = x0 + k;
-                    v[k] = 0;
+                    uint32_t e = 2;
                     if (x >= lo && x < hi) {
                         while (x >= nb) {
                             qq++;
@@ -1671,15 +1677,32 @@ struct Decoder {
                         }
                         if (bad[qq] || (x + 1 == nb && lb[qq] == A.in_bytes + 1)) {
                             // a bad line is a lone newline; a virtual newline is not in memory
-                            v[k] = (x + 1 == nb) ? '\n' : 0;
+                            e = (x + 1 == nb) ? 1u : 2u;
                         } else {
-                            v[k] = A.in[la[qq] + (x - qoff[qq])];
+                            e = (qq << 2) | ((x - qoff[qq]) << 11);
                         }
                     }
+                    pk[k] = e;
+                }
+                uint32_t v[16];
+                if (has_in) {
+                    // a byte that is not loaded reads A.in[0] (in bounds) instead
+#pragma unroll
+                    for (int k = 0; k < 16; k++) {
+                        const uint32_t e = pk[k];
+                        const uint64_t sa = (e & 3u) == 0 ? la[(e >> 2) & 511u] + (e >> 11) : 0;
+                        v[k] = A.in[sa];
+                    }
+                } else {
+#pragma unroll
+                    for (int k = 0; k < 16; k++) v[k] = 0;
                 }
 #pragma unroll
-                for (int k = 0; k < 16; k++)
-                    if (x0 + k >= lo && x0 + k < hi) cb[x0 + k] = v[k];
+                for (int k = 0; k < 16; k++) {
+                    const uint32_t kd = pk[k] & 3u;
+                    const uint8_t byte = kd == 0 ? (uint8_t)v[k] : kd == 1 ? (uint8_t)'\n' : (uint8_t)0;
+                    if (x0 + k >= lo && x0 + k < hi) cb[x0 + k] = byte;
+                }
             }
             __syncthreads();
         }
