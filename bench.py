@@ -441,7 +441,8 @@ def bench_random(args):
     the device and kept with its uint64 index; batches of 1k, 10k and 100k distinct uniform
     ids (10% of the 1k batches are one contiguous range instead), decompressed and packed in
     request order. Latency per batch is enqueue -> completion with the ids already on the
-    device, and again with the ids copied from pinned host memory inside the bracket. Every
+    device (all batches' ids are uploaded before the batches run), and again with the ids
+    copied from pinned host memory inside the bracket. Every
     20th batch is compared with the same lines cut out of a bulk decompression of the shard."""
     import torch
     import paper_2404_19391_amd as zs
@@ -479,16 +480,22 @@ def bench_random(args):
     for k in (1000, 10000, 100000):
         log("random access: %d batches of %d ids" % (nb, k))
         lat, lat_h2d, obytes, abytes, contiguous = [], [], [], [], 0
+        # every batch's ids are drawn and put on the device before the batches run, so
+        # that they run back to back (drawing 100k distinct ids takes the host ~6 ms,
+        # long enough for the idle GPU to lower its clocks before the next batch)
+        batches = []
         for it in range(nb + 3):
             if k == 1000 and rng.random() < 0.1:
                 start = int(rng.integers(0, n - k))
-                ids_h = np.arange(start, start + k, dtype=np.int64)
+                batches.append(np.arange(start, start + k, dtype=np.int64))
                 contiguous += it >= 3
             else:
-                ids_h = rng.choice(n, k, replace=False).astype(np.int64)
+                batches.append(rng.choice(n, k, replace=False).astype(np.int64))
+        ids_all = torch.from_numpy(np.concatenate(batches)).to(dev)
+        for it in range(nb + 3):
+            ids_h = batches[it]
             ids_pin[:k].copy_(torch.from_numpy(ids_h))
-            ids = ids_dev[:k]
-            ids.copy_(ids_pin[:k])
+            ids = ids_all[it * k:(it + 1) * k]
             torch.cuda.synchronize()
             e0, e1, e2 = (torch.cuda.Event(enable_timing=True) for _ in range(3))
             e0.record(stream)
@@ -497,8 +504,8 @@ def bench_random(args):
             e1.synchronize()
             # the same batch with the ids uploaded inside the bracket
             e2.record(stream)
-            ids.copy_(ids_pin[:k], non_blocking=True)
-            zs.decompress_lines_into(d, c, c_off, ids, out, out_off[:k + 1], ws, res)
+            ids_dev[:k].copy_(ids_pin[:k], non_blocking=True)
+            zs.decompress_lines_into(d, c, c_off, ids_dev[:k], out, out_off[:k + 1], ws, res)
             e3 = torch.cuda.Event(enable_timing=True)
             e3.record(stream)
             e3.synchronize()
@@ -522,6 +529,7 @@ def bench_random(args):
                           and torch.equal(out_off[1:k + 1], cum))
                 checked += 1
                 bad += not ok
+        del ids_all
         lat = np.array(lat)
         lat_h2d = np.array(lat_h2d)
         med = float(np.median(lat))
@@ -695,13 +703,17 @@ def main():
         rng = np.random.default_rng(45)
         for k in (1000, 10000, 100000):
             lat = []
+            # all batches' ids on the device first, so that the batches run back to back
+            batches = []
             for it in range(args.ra_batches + 3):
                 if rng.random() < 0.1 and k == 1000:
                     start = int(rng.integers(0, n - k))
-                    ids_h = np.arange(start, start + k, dtype=np.int64)
+                    batches.append(np.arange(start, start + k, dtype=np.int64))
                 else:
-                    ids_h = rng.choice(n, k, replace=False).astype(np.int64) if k < n else np.arange(n)
-                ids_d = torch.from_numpy(ids_h).to(dev)
+                    batches.append(rng.choice(n, k, replace=False).astype(np.int64) if k < n else np.arange(n))
+            ids_all = torch.from_numpy(np.concatenate(batches)).to(dev)
+            for it in range(args.ra_batches + 3):
+                ids_d = ids_all[it * k:(it + 1) * k]
                 torch.cuda.synchronize()
                 e0 = torch.cuda.Event(enable_timing=True)
                 e1 = torch.cuda.Event(enable_timing=True)

@@ -1493,7 +1493,9 @@ struct Decoder {
             pend = false;
         };
         while (true) {
-            const uint32_t t = claimed ? next : claim_tile(A.ws, &misc[kDmSlot]);
+            // with one workgroup per tile (the grid is never larger than the
+            // tile count) every workgroup's first ticket was its only tile
+            const uint32_t t = claimed ? next : gridDim.x >= A.ntiles ? A.ntiles : claim_tile(A.ws, &misc[kDmSlot]);
             claimed = false;
             if (t >= A.ntiles) {
                 if (pend) place_pending();
