@@ -250,6 +250,70 @@ def test_decompress_many_tiles(zs, gd, odict):
     assert host(got).tobytes() == want.tobytes()
 
 
+def _merge_lines(buf, off, every, span):
+    """Join lines s..s+span-1 into one line (newlines between them removed) for s = 100,
+    100 + every, ...: long lines made of valid tokens."""
+    n = off.size - 1
+    keep = np.ones(n, dtype=bool)
+    for s0 in range(100, n - span - 1, every):
+        keep[s0:s0 + span - 1] = False
+    nl = (off[1:] - 1).astype(np.int64)
+    mask = np.ones(buf.size, dtype=bool)
+    mask[nl[~keep]] = False
+    pos = np.cumsum(mask)
+    off2 = np.zeros(int(keep.sum()) + 1, dtype=np.uint64)
+    off2[1:] = pos[nl[keep]]
+    return buf[mask], off2
+
+
+def test_decompress_lines_edge_cases(zs, gd, odict):
+    """Random access with output over the cases the gather of the compressed bytes
+    treats apart: corrupt lines (undefined codes, dangling escapes), requests out of
+    range, empty lines, lines of a few KiB (a tile then takes several LDS batches), and
+    a last line that ends at the virtual newline past the buffer."""
+    # valid lines, some merged into lines of a few KiB; then corrupt short lines
+    a_buf, a_off = _merge_lines(*_random_compressed(odict, 20000, 95), 700, 100)
+    c_buf, c_off = _random_compressed(odict, 10000, 97, p_bad=0.003)
+    ends = (c_off[1:] - 2).astype(np.int64)
+    pick = ends[(np.arange(c_off.size - 1) % 501 == 7) & (c_off[1:] - c_off[:-1] > 1)]
+    c_buf[pick] = 0x20  # dangling escapes
+    buf = np.concatenate([a_buf, c_buf])
+    off = np.concatenate([a_off[:-1], c_off + a_off[-1]])
+    n = off.size - 1
+    assert int((off[1:] - off[:-1]).max()) > 1500
+    buf = buf[:-1].copy()  # the last line ends at the virtual newline: off[n] = len + 1
+    assert int(off[-1]) == buf.size + 1
+    lens = (off[1:] - off[:-1]).astype(np.int64)
+    long_ids = np.nonzero(lens > 1000)[0]
+    empty_ids = np.nonzero(lens == 1)[0]
+    assert long_ids.size > 10 and empty_ids.size > 10
+    rnd = np.random.default_rng(96)
+    b, o = dev(buf, off)
+    cases = [
+        rnd.integers(0, n, 5000),                                   # small tiles
+        rnd.integers(0, n, 60000),                                  # larger tiles
+        np.concatenate([np.repeat(long_ids, 4), empty_ids, [n - 1, 0, n - 1]]),  # several batches per tile
+        np.array([n - 1]),
+        np.array([5, n, 7, n + 3, n - 1]),                          # out of range
+    ]
+    for ids in cases:
+        ids = ids.astype(np.uint64)
+        code, fb, want, woff = oracle.decompress_lines(odict, buf, off, ids)
+        idsd = torch.from_numpy(ids.astype(np.int64)).cuda()
+        ws = zs.Workspaces().get(zs.OP_DECOMPRESS_LINES, ids.size)
+        out_off = torch.empty(ids.size + 1, dtype=torch.int64, device="cuda")
+        res = zs.new_result()
+        zs.decompress_lines_into(gd, b, o, idsd, None, out_off, ws, res)  # size-only
+        assert np.array_equal(host(out_off).astype(np.uint64), woff)
+        assert zs.read_result(res) == (code, fb)
+        out = torch.empty(max(int(woff[-1]), 1), dtype=torch.uint8, device="cuda")
+        res = zs.new_result()
+        zs.decompress_lines_into(gd, b, o, idsd, out, out_off, ws, res)
+        assert zs.read_result(res) == (code, fb)
+        assert np.array_equal(host(out_off).astype(np.uint64), woff)
+        assert host(out)[:int(woff[-1])].tobytes() == want.tobytes()
+
+
 @pytest.mark.parametrize("n", [3000, 400000])
 def test_decompress_corrupt_lines(zs, gd, odict, n):
     """Undefined codes and dangling escapes spread over many lines: the bad lines
