@@ -1602,6 +1602,60 @@ struct Decoder {
         finish_workgroup(A.ws, A.res, gridDim.x);
     }
 
+    // Gather of a batch whose lines are all short: lane q copies line q into CB
+    // at pos from the aligned dwords that hold it, all of them loaded before
+    // the first is used.  Returns false, having written nothing, when a line of
+    // the batch is longer than kLaneLine bytes or its dwords would reach outside
+    // [in, in + in_bytes); the caller then gathers by 16-byte chunks.
+    static constexpr uint32_t kLaneLine = 64;
+    static constexpr int kLaneDw = 17;  // dwords that hold kLaneLine bytes at any alignment
+    __device__ __forceinline__ bool gather_lanes(uint32_t q, uint32_t b0, uint32_t b1, uint32_t sz, uint32_t pos) {
+        const uint8_t* bad = BAD();
+        const uint64_t* la = LA();
+        const uint64_t* lb = LB();
+        uint8_t* cb = CB();
+        const bool mine = q >= b0 && q < b1;
+        const bool isbad = mine && bad[q] != 0;
+        // bytes of the line in memory (a virtual last newline is not)
+        uint32_t nreal = 0;
+        uintptr_t d0 = 0;
+        int ndw = 0;
+        bool ok = true;
+        if (mine && !isbad) {
+            nreal = (lb[q] == A.in_bytes + 1) ? sz - 1 : sz;
+            if (nreal > 0) {
+                const uintptr_t first = (uintptr_t)(A.in + la[q]);
+                d0 = first & ~(uintptr_t)3;
+                const uintptr_t dl = (first + nreal - 1) & ~(uintptr_t)3;
+                ndw = (int)((dl - d0) >> 2) + 1;
+                ok = nreal <= kLaneLine && d0 >= (uintptr_t)A.in && dl + 4 <= (uintptr_t)(A.in + A.in_bytes);
+            }
+        }
+        if (__syncthreads_or(!ok) != 0) return false;
+        if (nreal > 0) {
+            // pointer arithmetic on A.in (not integers) keeps these global loads
+            const uint8_t* first = A.in + la[q];
+            const int sh = (int)(((uintptr_t)first) & 3);
+            const uint32_t* dw = (const uint32_t*)(first - sh);
+            uint32_t w[kLaneDw];
+#pragma unroll
+            for (int k = 0; k < kLaneDw; k++) w[k] = dw[min(k, ndw - 1)];
+            __builtin_amdgcn_sched_barrier(0);  // every load issued before the first store
+#pragma unroll
+            for (int k = 0; k < kLaneDw; k++) {
+#pragma unroll
+                for (int b = 0; b < 4; b++) {
+                    const int idx = 4 * k + b - sh;
+                    if (idx >= 0 && idx < (int)nreal) cb[pos + idx] = (uint8_t)(w[k] >> (8 * b));
+                }
+            }
+        }
+        // a bad line is a lone newline; a virtual newline is written here
+        if (mine && (isbad || nreal < sz)) cb[pos + sz - 1] = '\n';
+        __syncthreads();
+        return true;
+    }
+
     // Choose the batch [b0, b1) that fits the CB buffer and load it.  Lines are
     // packed at qoff[q]; every line ends with its newline in CB (a line whose
     // last byte is not a newline is bad, and its last CB byte is made one so
@@ -1646,6 +1700,8 @@ struct Decoder {
             __syncthreads();
             if (tid == 0 && lb[b1 - 1] == A.in_bytes + 1) cb[qoff[b1] - 1] = '\n';
             __syncthreads();
+        } else if (gather_lanes(q, b0, b1, sz, pos)) {
+            // every line of the batch was copied by its own lane
         } else {
             // gather: each thread fills 16-byte chunks of CB; the line of a
             // chunk's first byte comes from a search of qoff.  The source
