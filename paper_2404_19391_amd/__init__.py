@@ -173,13 +173,14 @@ def _torch():
     return torch
 
 
+# Pointer arguments are passed as plain ints (None for NULL): every entry point has
+# c_void_p argtypes, so ctypes converts them without a wrapper object per argument.
 def _stream():
-    torch = _torch()
-    return _vp(torch.cuda.current_stream().cuda_stream)
+    return _torch().cuda.current_stream().cuda_stream
 
 
 def _p(t):
-    return _vp(t.data_ptr()) if t is not None and t.numel() else _vp(0)
+    return t.data_ptr() if t is not None and t.numel() else None
 
 
 def read_zsd(path):
