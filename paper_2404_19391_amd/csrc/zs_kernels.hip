@@ -2925,10 +2925,8 @@ static zs_status decompress_common(const zs_dict* d, const uint8_t* in, uint64_t
     }
     DeviceInfo di = device_info();
     if (!di.ok) return ZS_EDEVICE;
-    // small request sets are cut into smaller tiles so that more workgroups share
-    // them, down to half a tile per CU (at 10k requests, 157 tiles of 64 finished
-    // sooner than 313 of 32: fewer workgroups wait on the look-back and the counters)
-    const uint64_t want = (uint64_t)di.cus / 2;
+    // small request sets are cut into smaller tiles so that more workgroups share them
+    const uint64_t want = (uint64_t)di.cus * 2;
     uint32_t tl = kDL;
     while (tl > 32 && (nreq + tl - 1) / tl < want) tl >>= 1;
     const uint32_t ntiles = tiles_for(nreq, tl);
