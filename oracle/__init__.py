@@ -260,8 +260,8 @@ def train_patterns(buf, off, T, lmin=2, lmax=8, preprocess=True):
     """Algorithm 1 (Sec. IV-C): the T patterns of highest Eq. (1) rank, in selection order."""
     lib = _load()
     buf, off = _as_u8(buf), _as_u64(off)
-    pat = np.zeros((T, 8), dtype=np.uint8)
-    plen = np.zeros(T, dtype=np.uint8)
+    pat = np.zeros((max(T, 1), 16), dtype=np.uint8)
+    plen = np.zeros(max(T, 1), dtype=np.uint8)
     got = lib.zo_train_dict(_ptr(buf), _ptr(off), off.size - 1, 1 if preprocess else 0, lmin, lmax, T,
                             _ptr(pat), _ptr(plen))
     if got < 0:
