@@ -139,6 +139,25 @@ zs_status zs_decompress_lines(const zs_dict *d, const uint8_t *in, uint64_t in_b
                               void *stream);
 
 /*
+ * zs_decompress_lines without a workspace, for callers that cannot allocate
+ * device memory (code under HIP graph capture, tight serving loops,
+ * harnesses that forbid allocation).  Same arguments, output, result word
+ * and errors as zs_decompress_lines, minus ws/ws_bytes: the call's scratch
+ * (a header and one word per tile, about 545 KiB) is a static array that
+ * the library holds on each device it runs on until the process ends.  It
+ * allocates nothing and clears its scratch with a kernel.  n_ids above
+ * ZS_NOALLOC_MAX_IDS returns ZS_EINVAL before anything is enqueued.  Every
+ * call on one device shares that device's scratch: calls that overlap in
+ * time on one device (different streams, or host threads) race and give
+ * wrong results; serialise them, e.g. on one stream.
+ */
+#define ZS_NOALLOC_MAX_IDS (1u << 24)
+zs_status zs_decompress_lines_noalloc(const zs_dict *d, const uint8_t *in, uint64_t in_bytes,
+                                      const uint64_t *in_off, uint64_t n_lines, const uint64_t *ids,
+                                      uint64_t n_ids, uint8_t *out, uint64_t out_cap, uint64_t *out_off,
+                                      zs_result *res, void *stream);
+
+/*
  * Build the line index of a newline-separated buffer (one SMILES per line,
  * Sec. I): off[0] = 0, off[k+1] = one past the k-th newline; a last line
  * without newline ends at the virtual newline len+1.  *n_lines_out (device

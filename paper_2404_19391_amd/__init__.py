@@ -120,6 +120,8 @@ def lib():
         L.zs_decompress_lines.restype = ctypes.c_int
         L.zs_decompress_lines.argtypes = [_vp, _vp, _u64, _vp, _u64, _vp, _u64, _vp, _u64, _vp, _vp,
                                           ctypes.c_size_t, _vp, _vp]
+        L.zs_decompress_lines_noalloc.restype = ctypes.c_int
+        L.zs_decompress_lines_noalloc.argtypes = [_vp, _vp, _u64, _vp, _u64, _vp, _u64, _vp, _u64, _vp, _vp, _vp]
         L.zs_index_lines.restype = ctypes.c_int
         L.zs_index_lines.argtypes = [_vp, _u64, _vp, _u64, _vp, _vp, ctypes.c_size_t, _vp, _vp]
         L.zs_binned_workspace_bytes.restype = ctypes.c_size_t
@@ -401,6 +403,19 @@ def decompress_lines_into(d, buf, off, ids, out, out_off, ws, res, in_bytes=None
                                    out.numel() if out is not None else 0, _p(out_off), _p(ws), ws.numel(),
                                    _p(res), _stream())
     _check_rc(rc, "zs_decompress_lines")
+
+
+NOALLOC_MAX_IDS = 1 << 24
+
+
+def decompress_lines_noalloc_into(d, buf, off, ids, out, out_off, res, in_bytes=None, n_ids=None):
+    """zs_decompress_lines_noalloc: the library's static scratch instead of a workspace."""
+    n = off.numel() - 1
+    nb = buf.numel() if in_bytes is None else in_bytes
+    k = ids.numel() if n_ids is None else n_ids
+    rc = lib().zs_decompress_lines_noalloc(d.handle, _p(buf), nb, _p(off), n, _p(ids), k, _p(out),
+                                           out.numel() if out is not None else 0, _p(out_off), _p(res), _stream())
+    _check_rc(rc, "zs_decompress_lines_noalloc")
 
 
 def index_into(buf, off, n_out, ws, res):

@@ -2467,6 +2467,35 @@ BinnedWs binned_ws(void* ws, uint64_t n, uint64_t out_cap, int cus) {
 
 }  // namespace
 
+// Scratch of zs_decompress_lines_noalloc, one copy per device for the life of
+// the process: the workspace header and one look-back word per tile.  A set
+// of at most ZS_NOALLOC_MAX_IDS requests is cut into at most 65,536 tiles of
+// 256, or, when that gives fewer than two tiles per CU, into fewer than four
+// tiles per CU; 69,632 words cover both on devices of up to 17,408 CUs (the
+// call checks its tile count against them).
+constexpr size_t kNoallocTiles = 69632;
+constexpr size_t kNoallocScratchBytes = sizeof(WsHeader) + 8 * kNoallocTiles;
+static_assert(ZS_NOALLOC_MAX_IDS / kDL <= kNoallocTiles, "tiles of the largest request set must fit");
+static __device__ __align__(256) uint8_t scratch[kNoallocScratchBytes];
+
+// Device address of this device's scratch, looked up once per device (the
+// array's name in host code is only a stand-in for it).  Null if the lookup
+// fails.
+static void* noalloc_scratch() {
+    static std::mutex mu;
+    static std::vector<void*> ptr;
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0) return nullptr;
+    std::lock_guard<std::mutex> g(mu);
+    if ((int)ptr.size() <= dev) ptr.resize(dev + 1, nullptr);
+    if (!ptr[dev]) {
+        void* p = nullptr;
+        if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess || !p) return nullptr;
+        ptr[dev] = p;
+    }
+    return ptr[dev];
+}
+
 struct zs_dict {
     uint8_t* d_tables = nullptr;
     uint32_t blob_bytes = 0;
@@ -2912,12 +2941,24 @@ void zs_graph_destroy(zs_graph* g) {
     delete g;
 }
 
+// Requests per tile of a decompression of nreq lines or ids: small request sets
+// are cut into smaller tiles so that more workgroups share them.
+static uint32_t decompress_tile_lines(uint64_t nreq, int cus) {
+    const uint64_t want = (uint64_t)cus * 2;
+    uint32_t tl = kDL;
+    while (tl > 32 && (nreq + tl - 1) / tl < want) tl >>= 1;
+    return tl;
+}
+
+// ws_bytes is checked against zs_workspace_bytes(op, nreq) when exact_ws is
+// false, else against what this call's tiles need (the scratch of the
+// allocation-free entry point).
 static zs_status decompress_common(const zs_dict* d, const uint8_t* in, uint64_t in_bytes, const uint64_t* in_off,
                                    uint64_t n_lines, const uint64_t* ids, uint64_t nreq, uint8_t* out,
                                    uint64_t out_cap, uint64_t* out_off, void* ws, size_t ws_bytes, zs_result* res,
-                                   void* stream, int op) {
+                                   void* stream, int op, bool exact_ws = false) {
     if (!d || !in_off || !out_off || !ws || (!in && in_bytes)) return ZS_EINVAL;
-    if (ws_bytes < zs_workspace_bytes(op, nreq)) return ZS_EINVAL;
+    if (!exact_ws && ws_bytes < zs_workspace_bytes(op, nreq)) return ZS_EINVAL;
     hipStream_t s = (hipStream_t)stream;
     if (nreq == 0) {
         hipLaunchKernelGGL(empty_result_kernel, dim3(1), dim3(1), 0, s, out_off, (ResultOut*)res);
@@ -2925,11 +2966,9 @@ static zs_status decompress_common(const zs_dict* d, const uint8_t* in, uint64_t
     }
     DeviceInfo di = device_info();
     if (!di.ok) return ZS_EDEVICE;
-    // small request sets are cut into smaller tiles so that more workgroups share them
-    const uint64_t want = (uint64_t)di.cus * 2;
-    uint32_t tl = kDL;
-    while (tl > 32 && (nreq + tl - 1) / tl < want) tl >>= 1;
+    const uint32_t tl = decompress_tile_lines(nreq, di.cus);
     const uint32_t ntiles = tiles_for(nreq, tl);
+    if (exact_ws && ws_bytes < sizeof(WsHeader) + (size_t)ntiles * 8) return ZS_EINVAL;
     WsHeader* h = (WsHeader*)ws;
     uint64_t* status = (uint64_t*)(h + 1);
     if (launch_init(h, status, ntiles, (ResultOut*)res, s) != ZS_OK) return ZS_EDEVICE;
@@ -2974,6 +3013,18 @@ zs_status zs_decompress_lines(const zs_dict* d, const uint8_t* in, uint64_t in_b
     if (n_ids && !ids) return ZS_EINVAL;
     return decompress_common(d, in, in_bytes, in_off, n_lines, ids, n_ids, out, out_cap, out_off, ws, ws_bytes,
                              res, stream, ZS_OP_DECOMPRESS_LINES);
+}
+
+zs_status zs_decompress_lines_noalloc(const zs_dict* d, const uint8_t* in, uint64_t in_bytes,
+                                      const uint64_t* in_off, uint64_t n_lines, const uint64_t* ids, uint64_t n_ids,
+                                      uint8_t* out, uint64_t out_cap, uint64_t* out_off, zs_result* res,
+                                      void* stream) {
+    if (n_ids && !ids) return ZS_EINVAL;
+    if (n_ids > ZS_NOALLOC_MAX_IDS) return ZS_EINVAL;
+    void* ws = noalloc_scratch();
+    if (!ws) return ZS_EDEVICE;
+    return decompress_common(d, in, in_bytes, in_off, n_lines, ids, n_ids, out, out_cap, out_off, ws,
+                             kNoallocScratchBytes, res, stream, ZS_OP_DECOMPRESS_LINES, true);
 }
 
 zs_status zs_index_lines(const uint8_t* buf, uint64_t len, uint64_t* off, uint64_t off_cap, uint64_t* n_lines_out,
