@@ -69,6 +69,12 @@ typedef enum {
 
 #define ZS_LMAX_CAP 16u      /* longest expansion a dictionary may hold              */
 #define ZS_MAX_LINE 4096u    /* longest input line (bytes, newline excluded) accepted */
+/* Longest compressed line (bytes, newline excluded): zs_compress never emits a
+ * longer one (a line whose compressed form would be longer is bad, ZS_EINVAL:
+ * only ring renumbering that lengthens a line gets past 2 * ZS_MAX_LINE, the
+ * form of a longest line with every byte escaped), and the decoders take
+ * every line up to it (a longer one is bad, ZS_EINVAL). */
+#define ZS_MAX_CLINE 8192u
 #define ZS_F_PREPROCESS 0x1u /* renumber ring IDs before compressing (Sec. IV-A)      */
 
 /* Operations for zs_workspace_bytes. */
@@ -115,14 +121,16 @@ size_t zs_workspace_bytes(int op, uint64_t n);
  * line is replaced by the shortest string of codes and escapes (' ' + byte)
  * that decodes to it, the parse that takes the longest code first among the
  * shortest ones (Sec. IV-D-1).  Output framing as described above;
- * out_off has n_lines+1 entries.  Lines longer than ZS_MAX_LINE are bad
+ * out_off has n_lines+1 entries.  Lines longer than ZS_MAX_LINE, and lines
+ * whose compressed form would be longer than ZS_MAX_CLINE, are bad
  * (ZS_EINVAL).
  */
 zs_status zs_compress(const zs_dict *d, const uint8_t *in, uint64_t in_bytes, const uint64_t *in_off,
                       uint64_t n_lines, uint8_t *out, uint64_t out_cap, uint64_t *out_off, uint32_t flags,
                       void *ws, size_t ws_bytes, zs_result *res, void *stream);
 
-/* Decompress every line (Sec. IV-D-2).  out_off has n_lines+1 entries. */
+/* Decompress every line (Sec. IV-D-2).  out_off has n_lines+1 entries.  A
+ * compressed line longer than ZS_MAX_CLINE is bad (ZS_EINVAL). */
 zs_status zs_decompress(const zs_dict *d, const uint8_t *in, uint64_t in_bytes, const uint64_t *in_off,
                         uint64_t n_lines, uint8_t *out, uint64_t out_cap, uint64_t *out_off, void *ws,
                         size_t ws_bytes, zs_result *res, void *stream);
@@ -170,7 +178,7 @@ zs_status zs_index_lines(const uint8_t *buf, uint64_t len, uint64_t *off, uint64
 
 /*
  * Length-binned compression, for batches whose line lengths are very uneven
- * (the paper's compressor takes one block per SMILES, Sec. V; here lines are
+ * (the paper's compressor takes one block per SMILES, Sec. IV-E; here lines are
  * grouped by length so that the lanes of a wavefront hold lines of similar
  * length).  On the device, the lines are sorted by raw length into cfg->nbins
  * bins (a stable counting sort), every bin is compressed with its own tile
@@ -235,7 +243,10 @@ void zs_graph_destroy(zs_graph *g);
  * at submission into a pinned host arena of `host_bytes`; results come back
  * there.  zs_server_wait blocks until a request is done and describes its
  * result, which stays valid until zs_server_release.  Every result equals
- * what the same call gives on its own.
+ * what the same call gives on its own.  A request whose inputs fit but
+ * whose output (known after sizing) can never be held by the arenas, even
+ * with nothing else in them, ends with code ZS_ENOSPC and no offsets or
+ * bytes (off and data NULL).
  */
 typedef struct zs_server zs_server;
 typedef struct {

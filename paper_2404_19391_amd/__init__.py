@@ -550,7 +550,8 @@ class Server:
         r = Reply()
         _check_rc(lib().zs_server_wait(self.handle, ticket, ctypes.byref(r)), "zs_server_wait")
         n = int(r.n)
-        off = np.ctypeslib.as_array(r.off, shape=(n + 1,)).copy()
+        # a request that failed before its output was written has no offsets
+        off = np.ctypeslib.as_array(r.off, shape=(n + 1,)).copy() if r.off else np.zeros(0, dtype=np.uint64)
         data = np.ctypeslib.as_array(r.data, shape=(int(r.bytes),)).copy() if r.bytes else \
             np.zeros(0, dtype=np.uint8)
         t = {"submit": r.t_submit, "admit": r.t_admit, "done": r.t_done, "footprint": int(r.footprint)}

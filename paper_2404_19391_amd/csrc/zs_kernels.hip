@@ -734,6 +734,12 @@ struct Compressor {
                 cost = (v >> 5) - 1u;
             }
         }
+        // a compressed line longer than the decoder takes is bad, like a raw line
+        // longer than ZS_MAX_LINE (only renumbering that lengthens a line can get there)
+        if (st.in && !st.bad && cost > ZS_MAX_CLINE) {
+            st.bad = true;
+            note_error(A.ws, line_id(k0, b0 + st.j), kErrInval);
+        }
         if (st.in) COST()[b0 + st.j] = st.bad ? 0u : cost;
         st.esc = __syncthreads_or(esc_any) != 0;
         return b1;
@@ -1023,7 +1029,8 @@ __global__ void __launch_bounds__(kWG) compress_kernel(CompressArgs a) {
 
 constexpr int kDL = 256;                 // lines (or requests) per tile
 constexpr int kCbCap = 8192 + 16;        // LDS bytes of compressed lines per batch
-constexpr uint32_t kMaxCLine = 8191;     // longest compressed line accepted (newline excluded)
+constexpr uint32_t kMaxCLine = ZS_MAX_CLINE;  // longest compressed line accepted (newline excluded)
+static_assert(kMaxCLine + 1 + 15 <= (uint32_t)kCbCap, "a longest line, its newline and the lead must fit CB");
 constexpr int kSeg = kWG * 16;           // bytes per decode segment
 constexpr int kDStage = 16384;           // LDS output stage (a multiple of 16)
 
@@ -1097,7 +1104,7 @@ struct Decoder {
     __device__ __forceinline__ uint32_t* MISC() { return (uint32_t*)(smem + L.misc); }
     __device__ __forceinline__ uint8_t* STAGE() { return smem + L.stage; }
 
-    // One pass over the bytes [cb_lo, cb_hi) of lines [b0, b1) (Sec. IV-C: a
+    // One pass over the bytes [cb_lo, cb_hi) of lines [b0, b1) (Sec. IV-D-2: a
     // byte is a literal iff an odd run of spaces precedes it; a code expands to
     // its dictionary string).  Every line ends with its newline in CB.  Gives
     // each byte its output length and records line ends (batch-relative) in

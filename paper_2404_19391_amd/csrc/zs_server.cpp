@@ -268,6 +268,32 @@ bool start_running(zs_server* s, Slot& sl, Request* r) {
     return true;
 }
 
+// True if the request's output can never be held, even by arenas that hold
+// nothing else: the device arena must take its stage-1 buffers plus the
+// output, the host arena its pinned input plus the reply (offsets, bytes).
+bool never_fits(const zs_server* s, const Request* r) {
+    const uint64_t dev_need = stage1_bytes(r) + a256(r->total + 16);
+    const uint64_t host_need = a256(r->h_in_size + 16) + a256(64 + a256((r->n + 1) * 8) + r->total + 16) + 256;
+    return dev_need > s->dev.size() || host_need > s->host.size();
+}
+
+// End a request that failed before its output was written (reply: the code,
+// no offsets, no bytes).
+void finish_failed(zs_server* s, Slot& sl, Request* r, int32_t code) {
+    note(r, code);
+    r->total = 0;
+    free_device(s, r);
+    s->host.release(r->h_in);
+    r->h_in = nullptr;
+    r->stage = kDone;
+    r->t_done = now_s();
+    r->slot = -1;
+    sl.req = nullptr;
+    s->stats.completed++;
+    s->stats.busy_s += r->t_done - r->t_admit;
+    s->cv_done.notify_all();
+}
+
 void run_loop(zs_server* s) {
     (void)hipSetDevice(s->device);
     std::unique_lock<std::mutex> lk(s->mu);
@@ -283,6 +309,10 @@ void run_loop(zs_server* s) {
             note_hip(r, q);
             if (r->stage == kSizing) {
                 if (start_running(s, sl, r)) {
+                    progressed = true;
+                } else if (never_fits(s, r)) {
+                    // requeueing it would size it again forever
+                    finish_failed(s, sl, r, ZS_ENOSPC);
                     progressed = true;
                 } else {
                     // no room for the output: if no running request will free memory,
@@ -478,9 +508,9 @@ zs_status zs_server_wait(zs_server* s, uint64_t ticket, zs_reply* out) {
     out->code = r->fail ? r->fail : res.code;
     out->first_bad = r->fail ? -1 : res.first_bad;
     out->n = r->n;
-    out->off = (const uint64_t*)(r->h_out + 64);
-    out->data = r->h_out + 64 + a256((r->n + 1) * 8);
-    out->bytes = r->total;
+    out->off = r->fail ? nullptr : (const uint64_t*)(r->h_out + 64);
+    out->data = r->fail ? nullptr : r->h_out + 64 + a256((r->n + 1) * 8);
+    out->bytes = r->fail ? 0 : r->total;
     out->t_submit = r->t_submit;
     out->t_admit = r->t_admit;
     out->t_done = r->t_done;

@@ -90,11 +90,46 @@ def _nested(k):
     return b"C" + b"C".join(lab) + b"CC" + b"C".join(reversed(lab)) + b"C"
 
 
+def _growth_line(cycles, atom=b"C"):
+    """Digit ring labels only (never more than 10 rings open), built so that every
+    other ring, opened just before the previous one closes, holds closings of IDs
+    0..9 and gets ID 10: renumbering writes it as %10 and the line grows by 4 bytes."""
+    toks, free = [], list(range(10))
+
+    def op():
+        v = free.pop(0)
+        toks.append(atom + b"%d" % v)
+        return v
+
+    def cl(v):
+        toks.append(atom + b"%d" % v)
+        free.append(v)
+
+    def nest9():
+        vs = [op() for _ in range(9)]
+        for v in reversed(vs):
+            cl(v)
+
+    cur = op()
+    nest9()
+    for _ in range(cycles):
+        nxt = op()
+        cl(cur)
+        nest9()
+        cur = nxt
+    cl(cur)
+    return b"".join(toks) + atom
+
+
 def _edge_lines():
     rnd = np.random.default_rng(9)
     lines = [b"", b"C", b" ", b"  ", b"C C", b"   C  ", b"aei", b"~!@#", b"[NH3+]1CC[NH2+]C1",
              b"C1CC", b"C%1CC", b"[NH+1CC1", b"C1CC2CC1CC2", _nested(12), _nested(30), _nested(64),
              b"C" * 4096, b"c1ccccc1" * 512, b"(" * 100 + b")" * 100, b"%99C%99" * 10,
+             # longest compressed lines: every byte escaped (8,192 bytes, the decoders' limit)
+             b"a" * 4096, b" " * 4096,
+             # renumbering that lengthens a line past ZS_MAX_LINE (4,041 -> 4,241 bytes)
+             _growth_line(100),
              b"C1C2C3C4C5C6C7C8C9C%10C%11C%12C%13C%14C%15C%16C%17C1C2C3C4C5C6C7C8C9C%10C%11C%12C%13C%14C%15C%16C%17"]
     for _ in range(300):
         L = int(rnd.integers(0, 60))
@@ -109,6 +144,40 @@ def test_edge_lines(zs, gd, odict):
     got, goff, code, fb = _compare_compress(zs, gd, odict, buf, off)
     assert code == oracle.OK
     _compare_decompress(zs, gd, odict, host(got), host(goff))
+
+
+def test_growth_line_lengthens():
+    line = _growth_line(100)
+    assert len(line) <= 4096 < len(oracle.preprocess(line))
+
+
+def test_compressed_line_limit(zs, odict):
+    """A dictionary with one code ('C'): digits and '%' are escaped, so a line of
+    4,041 bytes whose renumbering lengthens it compresses to more than ZS_MAX_CLINE
+    bytes. The library rejects that line alone (ZS_EINVAL, empty line); the others,
+    a line at the limit among them, equal the oracle's and decode back."""
+    entries = {ord("C"): b"C"}
+    gdict = zs.Dict(entries)
+    lines = [b"CC", _growth_line(100, b"a"), b"a" * 4096, b"C1CC1", _growth_line(3, b"a")]
+    buf, off = oracle.join_lines(lines)
+    od = oracle.Dict(entries)
+    code, fb, want, woff = oracle.compress(od, buf, off)
+    assert code == oracle.OK
+    w = oracle.split_lines(want, woff)
+    assert len(w[1]) > 8192 and len(w[2]) == 8192
+    b, o = dev(buf, off)
+    got, goff = zs.compress(gdict, b, o, check=False)
+    res = zs.new_result()
+    ws = zs.Workspaces().get(zs.OP_COMPRESS, len(lines))
+    out = torch.empty(int(host(goff)[-1]), dtype=torch.uint8, device="cuda")
+    zs.compress_into(gdict, b, o, out, goff, ws, res)
+    assert zs.read_result(res) == (zs.EINVAL, 1)
+    g = oracle.split_lines(host(out), host(goff))
+    assert g[1] == b""
+    assert [g[i] for i in (0, 2, 3, 4)] == [w[i] for i in (0, 2, 3, 4)]
+    back, boff = zs.decompress(gdict, out, goff)
+    pb = oracle.split_lines(host(back), host(boff))
+    assert [pb[i] for i in (0, 2, 3, 4)] == [oracle.preprocess(lines[i]) for i in (0, 2, 3, 4)]
 
 
 def test_edge_lines_one_per_tile_boundary(zs, gd, odict):

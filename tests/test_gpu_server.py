@@ -138,3 +138,23 @@ def test_request_too_large(zs, gd, shard):
     with pytest.raises(zs.ZsError):
         srv.submit_decompress(sid, np.zeros(400000, dtype=np.uint64))
     srv.close()
+
+
+def test_output_that_can_never_fit_ends_with_enospc(zs, gd, odict):
+    """Inputs that fit the device arena but an output that cannot, even alone: the
+    request ends with ZS_ENOSPC (it used to be sized again forever), and the loop
+    goes on serving the requests behind it."""
+    buf, off = smilesgen.generate("long", 105, 3000)
+    code, fb, c, co = oracle.compress(odict, buf, off)
+    assert code == oracle.OK
+    srv, sid = _server(zs, gd, (c, co), slots=2, device_bytes=1 << 20, host_bytes=64 << 20)
+    ids = np.arange(3000, dtype=np.uint64)  # about 1.5 MB of output, 48 KB of stage-1 buffers
+    t_big = srv.submit_decompress(sid, ids)
+    t_small = srv.submit_decompress(sid, ids[:5])
+    got = srv.wait(t_big)
+    assert got[0] == zs.ENOSPC and got[2].size == 0 and got[3].size == 0
+    want = oracle.decompress_lines(odict, c, co, ids[:5])
+    assert _same(srv.wait(t_small), want)
+    st = srv.stats()
+    assert st["device_bytes_in_use"] == 0
+    srv.close()
