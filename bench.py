@@ -44,12 +44,14 @@ def parse():
     ap.add_argument("--seed", type=int, default=2)
     ap.add_argument("--ra-batches", type=int, default=200)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
-    ap.add_argument("--cpu-lines", type=int, default=800_000)
+    ap.add_argument("--cpu-lines", type=int, default=800_000, help="one-thread oracle sample")
+    ap.add_argument("--cpu-all-lines", type=int, default=3_200_000, help="all-cores oracle sample")
     ap.add_argument("--only", default="", help="comma list of ops to run (profiling runs)")
-    ap.add_argument("--workload", default="bulk", choices=["bulk", "uneven", "serve", "random"],
+    ap.add_argument("--workload", default="bulk", choices=["bulk", "uneven", "serve", "random", "dicts"],
                     help="bulk: the headline step; uneven: plain vs length-binned / autotuned / graph "
                          "compression; serve: the request loop under Poisson arrivals; random: random-access "
-                         "batches on a resident 40M-line shard")
+                         "batches on a resident 40M-line shard; dicts: the L_max sweep on the bulk workload "
+                         "and the Table I dictionary variants")
     ap.add_argument("--serve-requests", type=int, default=10000)
     ap.add_argument("--serve-gb", type=float, default=50.0, help="compressed shard bytes resident (GB)")
     ap.add_argument("--shard-lines", type=int, default=40_000_000)
@@ -74,10 +76,23 @@ def cpu_model():
     return platform.processor()
 
 
-def cpu_baseline(buf, off, n_sample):
-    """The oracle as it is, one thread, on the first n_sample lines of the same workload."""
+def compiler_version():
+    try:
+        return subprocess.run(["gcc", "--version"], stdout=subprocess.PIPE, text=True).stdout.splitlines()[0]
+    except (OSError, IndexError):
+        return "unknown"
+
+
+def cpu_baseline(buf, off, n_sample, n_all):
+    """The oracle as it is on the host: one thread on the first n_sample lines of the same
+    workload, and one process per usable core (at most 16) on the first n_all lines, each
+    process on its own contiguous ranges of lines (timed from handing out the work to
+    having every result back, the workers already started).  `value` is the all-cores
+    figure."""
     import oracle
-    d = oracle.Dict.load(os.path.join(ROOT, "paper_2404_19391_amd", "data", "default.zsd"))
+    from oracle import parallel
+    path = os.path.join(ROOT, "paper_2404_19391_amd", "data", "default.zsd")
+    d = oracle.Dict.load(path)
     n_sample = min(n_sample, off.size - 1)
     sb = buf[:int(off[n_sample])]
     so = off[:n_sample + 1]
@@ -88,17 +103,38 @@ def cpu_baseline(buf, off, n_sample):
     t2 = time.perf_counter()
     assert code == 0 and code2 == 0
     raw = float(sb.size)
+    one = {"value": round((raw + float(back.size)) / (t2 - t0) / 1e9, 6),
+           "compress_GBs": round(raw / (t1 - t0) / 1e9, 6),
+           "decompress_GBs": round(float(back.size) / (t2 - t1) / 1e9, 6),
+           "seconds": round(t2 - t0, 2),
+           "sample": "first %d lines (%.1f MB)" % (n_sample, raw / 1e6)}
+    # all cores: one worker process per core, disjoint line ranges; wall time includes
+    # starting the workers
+    n_all = min(n_all, off.size - 1)
+    ab = buf[:int(off[n_all])]
+    ao = off[:n_all + 1]
+    procs = parallel.default_procs()
+    with parallel.Pool(path, procs) as pool:
+        cc, _, ac, aco, cw, _ = pool.compress(ab, ao)
+        dc, _, aback, _, dw, _ = pool.decompress(ac, aco)
+    assert cc == 0 and dc == 0
+    araw, aout = float(ab.size), float(aback.size)
     return {
-        "value": round((raw + float(back.size)) / (t2 - t0) / 1e9, 6),
+        "value": round((araw + aout) / (cw + dw) / 1e9, 6),
         "unit": "GB/s",
-        "cores": 1,
+        "cores": procs,
         "kind": "oracle",
         "sample": "first %d lines of the bulk workload (%.1f MB): one compress and one decompress, "
-                  "single thread, in memory" % (n_sample, raw / 1e6),
-        "compress_GBs": round(raw / (t1 - t0) / 1e9, 6),
-        "decompress_GBs": round(float(back.size) / (t2 - t1) / 1e9, 6),
-        "seconds": round(t2 - t0, 2),
+                  "%d worker processes of one thread each on disjoint line ranges, in memory"
+                  % (n_all, araw / 1e6, procs),
+        "compress_GBs": round(araw / cw / 1e9, 6),
+        "decompress_GBs": round(aout / dw / 1e9, 6),
+        "seconds": round(cw + dw, 2),
+        "one_core": one,
         "cpu": cpu_model(),
+        "nproc": os.cpu_count(),
+        "affinity_cores": len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else None,
+        "compiler": compiler_version() + " -O2 (oracle/zs_oracle.c, no intrinsics, no threads)",
     }
 
 
@@ -160,6 +196,103 @@ def time_ms(fn, stream, reps):
         e1.synchronize()
         out.append(e0.elapsed_time(e1))
     return out
+
+
+DATA = os.path.join(ROOT, "paper_2404_19391_amd", "data")
+# L_max sweep (Sec. V-C): dictionary file, the L_max it was trained with
+SWEEP = [("lmax5", 5), ("default", 8), ("lmax15", 15), ("long16", 16)]
+# Table I (Sec. V-B): dictionary file, pre-processing, pre-population
+TABLE1 = [("t1_prep_printable", True, "Printable"), ("t1_raw_printable", False, "Printable"),
+          ("t1_prep_smiles", True, "SMILES alphabet"), ("t1_raw_smiles", False, "SMILES alphabet"),
+          ("t1_prep_none", True, "None"), ("t1_raw_none", False, "None")]
+
+
+def bench_dicts(args):
+    """The paper's two dictionary experiments on synthetic data.  L_max sweep (Sec. V-C,
+    Fig. 5): compression and decompression of the bulk workload with the dictionaries
+    trained at L_max 5, 8 and 15, and the long-pattern dictionary (16-wide parse window);
+    GB/s per kernel (median of --steps launches), ratio, and the first 200,000 lines of
+    each output checked against the oracle.  Table I (Sec. V-B): the six pre-processing x
+    pre-population dictionaries on their 50,000-line training set (train = test, as in
+    the paper), every output line checked against the oracle."""
+    import torch
+    import oracle
+    import paper_2404_19391_amd as zs
+    import smilesgen
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    stream = torch.cuda.current_stream()
+    n = args.lines
+    log("generating %d lines" % n)
+    buf, off = smilesgen.generate("bulk", args.seed, n, threads=16)
+    raw = int(buf.size)
+    b = torch.from_numpy(buf).to(dev)
+    o = torch.from_numpy(off.astype(np.int64)).to(dev)
+    ws = zs.Workspaces(dev)
+    res = zs.new_result(dev)
+    ncheck = min(n, 200_000)
+    sweep = []
+    for name, lmax in SWEEP:
+        path = os.path.join(DATA, name + ".zsd")
+        d = zs.Dict.load(path)
+        od = oracle.Dict.load(path)
+        c_off = torch.empty(n + 1, dtype=torch.int64, device=dev)
+        zs.compress_into(d, b, o, None, c_off, ws.get(zs.OP_COMPRESS, n), res)
+        ct = int(c_off[-1].item())
+        c = torch.empty(ct, dtype=torch.uint8, device=dev)
+        r = torch.empty(raw + 16, dtype=torch.uint8, device=dev)
+        r_off = torch.empty(n + 1, dtype=torch.int64, device=dev)
+        wc, wd = ws.get(zs.OP_COMPRESS, n), ws.get(zs.OP_DECOMPRESS, n)
+        fc = lambda: zs.compress_into(d, b, o, c, c_off, wc, res)  # noqa: E731
+        fd = lambda: zs.decompress_into(d, c, c_off, r, r_off, wd, res)  # noqa: E731
+        for _ in range(args.warmup):
+            fc()
+            fd()
+        tc = float(np.median(time_ms(fc, stream, args.steps)))
+        td = float(np.median(time_ms(fd, stream, args.steps)))
+        code, fb = zs.read_result(res)
+        assert code == 0, (name, code, fb)
+        dec = int(r_off[-1].item())
+        code, _, want, woff = oracle.compress(od, buf[:int(off[ncheck])], off[:ncheck + 1])
+        got = c[:int(c_off[ncheck].item())].cpu().numpy()
+        ok = code == 0 and got.tobytes() == want.tobytes() and \
+            np.array_equal(c_off[:ncheck + 1].cpu().numpy().astype(np.uint64), woff)
+        idx = 16 * (n + 1)
+        sweep.append({"dict": name, "trained_lmax": lmax, "longest_pattern": od.lmax,
+                      "parse_window": 8 if od.lmax <= 8 else 16, "ratio": round(ct / raw, 4),
+                      "compress_ms": round(tc, 4), "compress_user_GBs": round(raw / tc / 1e6, 2),
+                      "compress_hbm_alg_GBs": round((raw + ct + idx) / tc / 1e6, 2),
+                      "decompress_ms": round(td, 4), "decompress_user_GBs": round(dec / td / 1e6, 2),
+                      "decompress_hbm_alg_GBs": round((dec + ct + idx) / td / 1e6, 2),
+                      "oracle_match_first_%d_lines" % ncheck: bool(ok)})
+        log(json.dumps(sweep[-1]))
+        del c, r, r_off, c_off
+    del b, o
+    torch.cuda.empty_cache()
+    # Table I
+    tb, to = smilesgen.generate("small", 1001, 50000)
+    tbd = torch.from_numpy(tb).to(dev)
+    tod = torch.from_numpy(to.astype(np.int64)).to(dev)
+    table = []
+    for name, prep, pop in TABLE1:
+        path = os.path.join(DATA, name + ".zsd")
+        d = zs.Dict.load(path)
+        od = oracle.Dict.load(path)
+        c, co = zs.compress(d, tbd, tod, preprocess=prep)
+        code, _, want, woff = oracle.compress(od, tb, to, preprocess=prep)
+        ok = code == 0 and c.cpu().numpy().tobytes() == want.tobytes() and \
+            np.array_equal(co.cpu().numpy().astype(np.uint64), woff)
+        table.append({"pre_processing": "Yes" if prep else "No", "pre_population": pop,
+                      "ratio": round(c.numel() / tb.size, 4), "oracle_match_all_lines": bool(ok)})
+        log(json.dumps(table[-1]))
+    out = {
+        "metric": METRIC, "value": None, "unit": "GB/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "higher_is_better": True, "dtype": "u8", "data": "synthetic",
+        "config": {"workload": "dictionary variants: L_max sweep on %d bulk lines (%.3f GB raw); Table I "
+                               "on 50,000 small-workload lines (train = test)" % (n, raw / 1e9)},
+        "lmax_sweep": sweep, "table1": table,
+    }
+    print(json.dumps(out), flush=True)
 
 
 def bench_uneven(args):
@@ -590,6 +723,8 @@ def main():
         return bench_serve(args)
     if args.workload == "random":
         return bench_random(args)
+    if args.workload == "dicts":
+        return bench_dicts(args)
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
     only = set(args.only.split(",")) if args.only else {"index", "compress", "decompress", "random"}
@@ -776,7 +911,7 @@ def main():
     }
     if not args.no_cpu:
         log("cpu baseline on %d lines" % args.cpu_lines)
-        out["cpu_baseline"] = cpu_baseline(buf, off, args.cpu_lines)
+        out["cpu_baseline"] = cpu_baseline(buf, off, args.cpu_lines, args.cpu_all_lines)
     print(json.dumps(out), flush=True)
 
 

@@ -2,9 +2,9 @@
 byte for byte (the codec is exact integer/byte work, so the tolerance is zero).
 
 Sizes: the 10,000-line small workload end to end; smaller adversarial sets that span
-many tiles and ragged tails; and the 10M-line bulk workload at full size, where every
-line is checked by round trip against the oracle's pre-processing and a random sample
-of lines against the oracle's compressor."""
+many tiles and ragged tails; and, at full size, the 10M-line bulk workload and the 20M-line
+uneven workload, every compressed line against the oracle (run as host processes on
+disjoint line ranges)."""
 import numpy as np
 import pytest
 
@@ -451,23 +451,27 @@ def test_determinism(zs, gd, odict):
 
 @pytest.mark.slow
 def test_bulk_workload_full_size(zs, gd, odict):
-    """10M lines: every line by round trip, 20,000 random lines against the oracle."""
+    """10M lines: every compressed line and offset against the oracle (run as host
+    processes on disjoint line ranges), the bulk decode against the oracle's
+    pre-processing, random access against the rows of the bulk decode."""
+    from oracle import parallel
+    from conftest import DEFAULT_DICT
     n = 10_000_000
     buf, off = smilesgen.generate("bulk", 2, n)
     b, o = dev(buf, off)
     c, coff = zs.compress(gd, b, o)
     ch, cho = host(c), host(coff).astype(np.uint64)
-    rnd = np.random.default_rng(11)
-    sample = np.sort(rnd.choice(n, 20000, replace=False))
-    raw = buf.tobytes()
-    for k in sample:
-        x = raw[int(off[k]):int(off[k + 1]) - 1]
-        assert ch[int(cho[k]):int(cho[k + 1]) - 1].tobytes() == oracle.compress_line(odict, x), k
+    code, fb, want, woff, wall, cpu = parallel.compress(DEFAULT_DICT, buf, off)
+    print("oracle: %d lines in %.1f s wall, %.1f s summed over processes" % (n, wall, cpu), flush=True)
+    assert code == 0
+    assert np.array_equal(cho, woff)
+    assert ch.tobytes() == want.tobytes()
     back, boff = zs.decompress(gd, c, coff)
     p, po = oracle.preprocess_buffer(buf, off)
     assert np.array_equal(host(boff).astype(np.uint64), po)
     assert torch.equal(back, torch.from_numpy(p).cuda())
     # random access at full size against the rows of the bulk decode
+    rnd = np.random.default_rng(11)
     ids = rnd.integers(0, n, 100000).astype(np.int64)
     s, so = zs.decompress_lines(gd, c, coff, torch.from_numpy(ids).cuda())
     sh, soh = host(s), host(so)
@@ -475,3 +479,29 @@ def test_bulk_workload_full_size(zs, gd, odict):
     for r in range(0, 100000, 97):
         k = int(ids[r])
         assert sh[int(soh[r]):int(soh[r + 1])].tobytes() == ph[int(po[k]):int(po[k + 1])].tobytes()
+
+
+@pytest.mark.slow
+def test_uneven_workload_full_size(zs, gd, odict):
+    """20M uneven lines (2.2 GB): the plain and the binned compression, each
+    against the oracle line for line (host processes on disjoint line ranges)."""
+    from oracle import parallel
+    from conftest import DEFAULT_DICT
+    n = 20_000_000
+    buf, off = smilesgen.generate("uneven", 3, n)
+    b, o = dev(buf, off)
+    c, coff = zs.compress(gd, b, o)
+    ch, cho = host(c), host(coff).astype(np.uint64)
+    del c, coff
+    cfg = zs.BinConfig.make(edges=(128,), lines_per_tile=(256, 32), large_lds=(0, 1))
+    bc, bco = zs.compress_binned(gd, b, o, cfg)
+    bh, bho = host(bc), host(bco).astype(np.uint64)
+    del bc, bco, b, o
+    torch.cuda.empty_cache()
+    code, fb, want, woff, wall, cpu = parallel.compress(DEFAULT_DICT, buf, off)
+    print("oracle: %d lines in %.1f s wall, %.1f s summed over processes" % (n, wall, cpu), flush=True)
+    assert code == 0
+    assert np.array_equal(cho, woff) and np.array_equal(bho, woff)
+    wb = want.tobytes()
+    assert ch.tobytes() == wb
+    assert bh.tobytes() == wb
