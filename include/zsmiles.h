@@ -285,6 +285,64 @@ zs_status zs_server_get_stats(zs_server *s, zs_server_stats *out);
 /* Finishes the admitted and queued requests, then frees everything. */
 void zs_server_destroy(zs_server *s);
 
+/*
+ * Ring-ID pre-processing alone (Sec. IV-A): every line of `in` is written
+ * with its ring-closure labels renumbered, exactly the form zs_compress
+ * parses under ZS_F_PREPROCESS (and the form decompression gives back).
+ * Framing, errors (bad lines come out empty), size-only mode and ENOSPC as
+ * for zs_compress; a line grows at most 3x (a digit label may become %nn),
+ * so 3 * in_bytes + n_lines bytes always suffice.  ws: zs_workspace_bytes(
+ * ZS_OP_COMPRESS, n_lines).
+ */
+zs_status zs_preprocess(const uint8_t *in, uint64_t in_bytes, const uint64_t *in_off, uint64_t n_lines,
+                        uint8_t *out, uint64_t out_cap, uint64_t *out_off, void *ws, size_t ws_bytes,
+                        zs_result *res, void *stream);
+
+/*
+ * Post-processing of decompressed lines.  The paper's execution flow
+ * (Sec. IV-D) lets decompressed SMILES be "optionally post-processed" without
+ * defining the step; the definition taken here: ring-closure labels are
+ * renumbered the way SMILES writers usually number them - reading left to
+ * right, a ring's opening label takes the smallest label >= 1 not held by a
+ * ring open at that point, and its closing label repeats it (1..9 as a digit,
+ * 10..99 as %nn).  Tokens, pairing and malformed lines (left unchanged) as in
+ * pre-processing; a line that would need label 100 is left unchanged.  Lines
+ * longer than ZS_MAX_LINE are bad (ZS_EINVAL).  Arguments, framing, errors,
+ * size-only mode and workspace as for zs_preprocess (3 * in_bytes + n_lines
+ * bytes always suffice).
+ */
+zs_status zs_postprocess(const uint8_t *in, uint64_t in_bytes, const uint64_t *in_off, uint64_t n_lines,
+                         uint8_t *out, uint64_t out_cap, uint64_t *out_off, void *ws, size_t ws_bytes,
+                         zs_result *res, void *stream);
+
+/*
+ * Dictionary generation, Algorithm 1 of Sec. IV-C, on the device.  Counts
+ * every substring of lmin..lmax bytes of every line (overlapping occurrences
+ * included; of the pre-processed lines when flags has ZS_F_PREPROCESS, as the
+ * paper trains its dictionaries, Sec. V-B), then T times takes the substring
+ * of highest rank occ * (len - overlap) (Eq. (1)), where overlap is the
+ * longest common substring with any pattern taken before (the reading of the
+ * paper's update_rank); ties go to the longer, then the bytewise smaller
+ * substring.  It stops early when no substring has a positive rank.
+ * Outputs (device): pat[t*16 .. t*16+pat_len[t]) is the t-th pattern taken,
+ * zero padded to 16 bytes; *n_chosen (uint32) how many were taken.  The
+ * caller assigns code bytes (Sec. IV-B: e.g. after the SMILES alphabet).
+ * Lines follow the rules of zs_compress (bytes 0x20..0x7E, at most
+ * ZS_MAX_LINE); any bad line makes the call fail: res->code and first_bad
+ * as for compression, *n_chosen = 0.  1 <= lmin <= lmax <= 16, T <=
+ * ZS_TRAIN_MAX_T, else ZS_EINVAL.  ws: zs_train_workspace_bytes(...) bytes,
+ * which grows with in_bytes * (lmax - lmin + 1) (an open-addressing table with
+ * room for every occurrence: about 40 bytes per occurrence, 3x that with
+ * pre-processing, whose lines may grow).  Enqueue-only like the other calls
+ * (2T + 6 kernel launches).
+ */
+#define ZS_TRAIN_MAX_T 4096u
+size_t zs_train_workspace_bytes(uint64_t in_bytes, uint64_t n_lines, uint32_t lmin, uint32_t lmax, uint32_t flags);
+zs_status zs_train_patterns(const uint8_t *in, uint64_t in_bytes, const uint64_t *in_off, uint64_t n_lines,
+                            uint32_t flags, uint32_t lmin, uint32_t lmax, uint32_t T, uint8_t *pat,
+                            uint8_t *pat_len, uint32_t *n_chosen, void *ws, size_t ws_bytes, zs_result *res,
+                            void *stream);
+
 /* Human-readable name of a status code. */
 const char *zs_status_str(int code);
 

@@ -66,6 +66,10 @@ def _load():
         L.zo_index_lines.restype = ctypes.c_int64
         L.zo_preprocess_buffer.argtypes = [_vp, _vp, ctypes.c_uint64, _vp, _vp]
         L.zo_preprocess_buffer.restype = None
+        L.zo_postprocess.argtypes = [_vp, ctypes.c_int64, _vp]
+        L.zo_postprocess.restype = ctypes.c_int64
+        L.zo_postprocess_buffer.argtypes = [_vp, _vp, ctypes.c_uint64, _vp, _vp]
+        L.zo_postprocess_buffer.restype = None
         L.zo_train_dict.argtypes = [_vp, _vp, ctypes.c_uint64, ctypes.c_int, ctypes.c_int, ctypes.c_int,
                                     ctypes.c_int, _vp, _vp]
         L.zo_train_dict.restype = ctypes.c_int
@@ -145,6 +149,27 @@ def preprocess_buffer(buf, off):
     out = np.zeros(3 * buf.size + n + 1, dtype=np.uint8)
     out_off = np.zeros(n + 1, dtype=np.uint64)
     lib.zo_preprocess_buffer(_ptr(buf), _ptr(off), n, out.ctypes.data_as(_vp), _ptr(out_off))
+    return out[:int(out_off[n])], out_off
+
+
+def postprocess(line):
+    """Post-processing of one decompressed line: ring labels renumbered in the writers'
+    convention (our definition; the paper names the step, Sec. IV-D, without defining it)."""
+    lib = _load()
+    x = _bytes_arr(line)
+    y = np.zeros(3 * x.size + 1, dtype=np.uint8)
+    m = lib.zo_postprocess(_ptr(x), x.size, _ptr(y))
+    return y[:m].tobytes()
+
+
+def postprocess_buffer(buf, off):
+    """Post-process every line of a buffer; returns (bytes, offsets)."""
+    lib = _load()
+    buf, off = _as_u8(buf), _as_u64(off)
+    n = off.size - 1
+    out = np.zeros(3 * buf.size + n + 1, dtype=np.uint8)
+    out_off = np.zeros(n + 1, dtype=np.uint64)
+    lib.zo_postprocess_buffer(_ptr(buf), _ptr(off), n, out.ctypes.data_as(_vp), _ptr(out_off))
     return out[:int(out_off[n])], out_off
 
 

@@ -15,6 +15,10 @@ calls zs_oracle.c, and the algorithms are different ones:
   equals the oracle's "smallest ID not held by a ring closed inside me", by a
   one-line argument (an ID is held by a ring closed inside R iff its latest
   close before R's closing label falls after R's opening label);
+* postprocess_alt computes the post-processing labels from ring intervals
+  instead of a left-to-right walk: a ring's label is the smallest label >= 1
+  not used by a ring whose interval contains the ring's opening label, taking
+  the rings in order of their opening labels;
 * ring_intervals / omega give the ring structure of a line for properties
   such as "nested rings get distinct IDs, inner lower" (Sec. II, Sec. IV-A).
 """
@@ -199,4 +203,39 @@ def decompress_ref(entries, c):
                 return None
             out += entries[c[j]]
             j += 1
+    return bytes(out)
+
+
+def postprocess_alt(s):
+    """Writers' ring numbering (our definition of post-processing) from ring intervals."""
+    s = bytes(s)
+    toks = _label_tokens(s)
+    rings = ring_intervals(s)
+    if toks is None or rings is None:
+        return s
+    label = {}
+    for o, c in sorted(rings):  # by opening token
+        used = {label[(o2, c2)] for (o2, c2) in label if o2 < o < c2}
+        v = 1
+        while v in used:
+            v += 1
+        if v > 99:
+            return s
+        label[(o, c)] = v
+    new_of_tok = {}
+    for (o, c), v in label.items():
+        new_of_tok[o] = v
+        new_of_tok[c] = v
+    out = bytearray()
+    i = 0
+    ti = 0
+    while i < len(s):
+        if ti < len(toks) and toks[ti][0] == i:
+            v = new_of_tok[ti]
+            out += (b"%d" % v) if v < 10 else (b"%%%02d" % v)
+            i = toks[ti][1]
+            ti += 1
+        else:
+            out.append(s[i])
+            i += 1
     return bytes(out)

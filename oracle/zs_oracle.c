@@ -227,6 +227,105 @@ int64_t zo_preprocess(const uint8_t *x, int64_t n, uint8_t *y) {
 }
 
 /* ------------------------------------------------------------------------ */
+/* Post-processing after decompression (Sec. IV-D: "optionally               */
+/* post-processed"; the paper gives no definition, the one below is ours)    */
+/* ------------------------------------------------------------------------ */
+
+/*
+ * Relabel the ring closures of one decompressed line the way SMILES writers
+ * usually number them: reading left to right, a ring's opening label takes
+ * the smallest label >= 1 that no ring open at that point holds, and its
+ * closing label repeats it.  Labels 1..9 are one digit, 10..99 '%' and two
+ * digits.  Tokens, pairing and malformed lines as in zo_preprocess (labels
+ * are digits or '%nn' outside brackets; the first label of a value opens a
+ * ring, the next closes it); a malformed line, or one that would need a label
+ * above 99, is copied unchanged.  Writes y (capacity >= 3*n) and returns its
+ * length.
+ */
+int64_t zo_postprocess(const uint8_t *x, int64_t n, uint8_t *y) {
+    /* label tokens: position, token length, value */
+    int64_t *pos = (int64_t *)malloc(sizeof(int64_t) * (size_t)(n + 1));
+    int *tlen = (int *)malloc(sizeof(int) * (size_t)(n + 1));
+    int *val = (int *)malloc(sizeof(int) * (size_t)(n + 1));
+    int *newl = (int *)malloc(sizeof(int) * (size_t)(n + 1));
+    int nt = 0, inbr = 0, bad = 0;
+    for (int64_t i = 0; i < n && !bad; i++) {
+        int c = x[i];
+        if (c == '[') {
+            if (inbr) bad = 1;
+            inbr = 1;
+        } else if (c == ']') {
+            if (!inbr) bad = 1;
+            inbr = 0;
+        } else if (!inbr && is_digit(c)) {
+            pos[nt] = i; tlen[nt] = 1; val[nt] = c - '0'; nt++;
+        } else if (!inbr && c == '%') {
+            if (i + 2 < n && is_digit(x[i + 1]) && is_digit(x[i + 2])) {
+                pos[nt] = i; tlen[nt] = 3; val[nt] = (x[i + 1] - '0') * 10 + (x[i + 2] - '0'); nt++;
+                i += 2;
+            } else {
+                bad = 1;
+            }
+        }
+    }
+    if (inbr) bad = 1;
+    /* walk the tokens in order: an opening takes the smallest free label >= 1,
+       the closing of the same value gives it back */
+    int open_tok[100], held[101];
+    for (int v = 0; v < 100; v++) open_tok[v] = -1;
+    for (int v = 0; v <= 100; v++) held[v] = 0;
+    for (int j = 0; j < nt && !bad; j++) {
+        int v = val[j];
+        if (open_tok[v] < 0) {
+            int l = 1;
+            while (l < 100 && held[l]) l++;
+            if (l >= 100) {
+                bad = 1;
+                break;
+            }
+            held[l] = 1;
+            newl[j] = l;
+            open_tok[v] = j;
+        } else {
+            int l = newl[open_tok[v]];
+            newl[j] = l;
+            held[l] = 0;
+            open_tok[v] = -1;
+        }
+    }
+    for (int v = 0; v < 100 && !bad; v++)
+        if (open_tok[v] >= 0) bad = 1;
+    int64_t m = 0;
+    if (bad) {
+        memcpy(y, x, (size_t)n);
+        m = n;
+    } else {
+        int j = 0;
+        for (int64_t i = 0; i < n;) {
+            if (j < nt && pos[j] == i) {
+                int l = newl[j];
+                if (l < 10) {
+                    y[m++] = (uint8_t)('0' + l);
+                } else {
+                    y[m++] = '%';
+                    y[m++] = (uint8_t)('0' + l / 10);
+                    y[m++] = (uint8_t)('0' + l % 10);
+                }
+                i += tlen[j];
+                j++;
+            } else {
+                y[m++] = x[i++];
+            }
+        }
+    }
+    free(pos);
+    free(tlen);
+    free(val);
+    free(newl);
+    return m;
+}
+
+/* ------------------------------------------------------------------------ */
 /* Compression of one line (Sec. IV-D-1)                                     */
 /* ------------------------------------------------------------------------ */
 
@@ -506,6 +605,17 @@ void zo_preprocess_buffer(const uint8_t *in, const uint64_t *in_off, uint64_t n,
     for (uint64_t k = 0; k < n; k++) {
         int64_t xl = (int64_t)(in_off[k + 1] - in_off[k] - 1);
         int64_t m = zo_preprocess(in + in_off[k], xl, out + out_off[k]);
+        out[out_off[k] + (uint64_t)m] = '\n';
+        out_off[k + 1] = out_off[k] + (uint64_t)m + 1;
+    }
+}
+
+/* Post-process every line of a buffer (same framing rules as zo_preprocess_buffer). */
+void zo_postprocess_buffer(const uint8_t *in, const uint64_t *in_off, uint64_t n, uint8_t *out, uint64_t *out_off) {
+    out_off[0] = 0;
+    for (uint64_t k = 0; k < n; k++) {
+        int64_t xl = (int64_t)(in_off[k + 1] - in_off[k] - 1);
+        int64_t m = zo_postprocess(in + in_off[k], xl, out + out_off[k]);
         out[out_off[k] + (uint64_t)m] = '\n';
         out_off[k + 1] = out_off[k] + (uint64_t)m + 1;
     }

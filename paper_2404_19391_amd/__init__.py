@@ -157,6 +157,15 @@ def lib():
         L.zs_server_get_stats.argtypes = [_vp, ctypes.POINTER(ServerStats)]
         L.zs_server_destroy.restype = None
         L.zs_server_destroy.argtypes = [_vp]
+        L.zs_preprocess.restype = ctypes.c_int
+        L.zs_preprocess.argtypes = [_vp, _u64, _vp, _u64, _vp, _u64, _vp, _vp, ctypes.c_size_t, _vp, _vp]
+        L.zs_postprocess.restype = ctypes.c_int
+        L.zs_postprocess.argtypes = [_vp, _u64, _vp, _u64, _vp, _u64, _vp, _vp, ctypes.c_size_t, _vp, _vp]
+        L.zs_train_workspace_bytes.restype = ctypes.c_size_t
+        L.zs_train_workspace_bytes.argtypes = [_u64, _u64, ctypes.c_uint32, ctypes.c_uint32, ctypes.c_uint32]
+        L.zs_train_patterns.restype = ctypes.c_int
+        L.zs_train_patterns.argtypes = [_vp, _u64, _vp, _u64, ctypes.c_uint32, ctypes.c_uint32, ctypes.c_uint32,
+                                        ctypes.c_uint32, _vp, _vp, _vp, _vp, ctypes.c_size_t, _vp, _vp]
         L.zsi_compile_dict_c.restype = ctypes.c_int
         L.zsi_compile_dict_c.argtypes = [_vp, _vp, _vp, _u64, ctypes.POINTER(_u64)]
         _lib = L
@@ -322,6 +331,37 @@ def compress_into(d, buf, off, out, out_off, ws, res, preprocess=True, in_bytes=
     _check_rc(rc, "zs_compress")
 
 
+def preprocess_into(buf, off, out, out_off, ws, res, in_bytes=None):
+    """zs_preprocess on preallocated tensors (ws: the OP_COMPRESS workspace); out may be None."""
+    n = off.numel() - 1
+    nb = buf.numel() if in_bytes is None else in_bytes
+    rc = lib().zs_preprocess(_p(buf), nb, _p(off), n, _p(out), out.numel() if out is not None else 0,
+                             _p(out_off), _p(ws), ws.numel(), _p(res), _stream())
+    _check_rc(rc, "zs_preprocess")
+
+
+def postprocess_into(buf, off, out, out_off, ws, res, in_bytes=None):
+    """zs_postprocess on preallocated tensors (ws: the OP_COMPRESS workspace); out may be None."""
+    n = off.numel() - 1
+    nb = buf.numel() if in_bytes is None else in_bytes
+    rc = lib().zs_postprocess(_p(buf), nb, _p(off), n, _p(out), out.numel() if out is not None else 0,
+                              _p(out_off), _p(ws), ws.numel(), _p(res), _stream())
+    _check_rc(rc, "zs_postprocess")
+
+
+def train_workspace_bytes(in_bytes, n, lmin, lmax, preprocess=True):
+    return int(lib().zs_train_workspace_bytes(in_bytes, n, lmin, lmax, F_PREPROCESS if preprocess else 0))
+
+
+def train_patterns_into(buf, off, T, lmin, lmax, preprocess, pat, pat_len, n_chosen, ws, res, in_bytes=None):
+    """zs_train_patterns on preallocated tensors: pat uint8 [T, 16], pat_len uint8 [T], n_chosen int32 [1]."""
+    n = off.numel() - 1
+    nb = buf.numel() if in_bytes is None else in_bytes
+    rc = lib().zs_train_patterns(_p(buf), nb, _p(off), n, F_PREPROCESS if preprocess else 0, lmin, lmax, T,
+                                 _p(pat), _p(pat_len), _p(n_chosen), _p(ws), ws.numel(), _p(res), _stream())
+    _check_rc(rc, "zs_train_patterns")
+
+
 def binned_workspace_bytes(n, out_cap):
     return int(lib().zs_binned_workspace_bytes(n, out_cap))
 
@@ -466,6 +506,48 @@ def compress_binned(d, buf, off, cfg, preprocess=True, check=True):
         compress_binned_into(d, buf, off, out, out_off, cfg, ws, res, preprocess)
 
     return _sized(run, out_off, dev, check, "compress_binned")
+
+
+def preprocess(buf, off, check=True):
+    """Ring-ID pre-processing of every line (Sec. IV-A); returns (bytes, offsets)."""
+    torch = _torch()
+    n = off.numel() - 1
+    dev = buf.device if buf.numel() else off.device
+    out_off = torch.empty(n + 1, dtype=torch.int64, device=dev)
+    ws = _ws_for(dev).get(OP_COMPRESS, n)
+    return _sized(lambda out, res: preprocess_into(buf, off, out, out_off, ws, res), out_off, dev, check,
+                  "preprocess")
+
+
+def postprocess(buf, off, check=True):
+    """Post-processing of decompressed lines: ring labels renumbered in the writers'
+    convention (the library's definition of the step Sec. IV-D names); (bytes, offsets)."""
+    torch = _torch()
+    n = off.numel() - 1
+    dev = buf.device if buf.numel() else off.device
+    out_off = torch.empty(n + 1, dtype=torch.int64, device=dev)
+    ws = _ws_for(dev).get(OP_COMPRESS, n)
+    return _sized(lambda out, res: postprocess_into(buf, off, out, out_off, ws, res), out_off, dev, check,
+                  "postprocess")
+
+
+def train_patterns(buf, off, T, lmin=2, lmax=8, preprocess=True, check=True):
+    """Algorithm 1 (Sec. IV-C) on the device: the T substrings of highest Eq. (1) rank, in
+    selection order, as a list of bytes (fewer when no candidate has a positive rank)."""
+    torch = _torch()
+    n = off.numel() - 1
+    dev = buf.device if buf.numel() else off.device
+    ws = torch.empty(max(train_workspace_bytes(buf.numel(), n, lmin, lmax, preprocess), 64), dtype=torch.uint8,
+                     device=dev)
+    pat = torch.zeros((max(T, 1), 16), dtype=torch.uint8, device=dev)
+    plen = torch.zeros(max(T, 1), dtype=torch.uint8, device=dev)
+    nch = torch.zeros(1, dtype=torch.int32, device=dev)
+    res = new_result(dev)
+    train_patterns_into(buf, off, T, lmin, lmax, preprocess, pat, plen, nch, ws, res)
+    _check_res(res, "train_patterns", check)
+    k = int(nch.item())
+    ph, lh = pat.cpu().numpy(), plen.cpu().numpy()
+    return [ph[i, :lh[i]].tobytes() for i in range(k)]
 
 
 def decompress(d, buf, off, check=True):

@@ -10,7 +10,7 @@ PKG = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 LIB = os.path.join(PKG, "libzsmiles.so")
-SOURCES = ["zs_kernels.hip", "zs_dict.cpp", "zs_server.cpp"]
+SOURCES = ["zs_kernels.hip", "zs_train.hip", "zs_dict.cpp", "zs_server.cpp"]
 HEADERS = ["zs_common.hpp", "zs_tables.hpp", os.path.join("..", "..", "include", "zsmiles.h")]
 ARCH = os.environ.get("ZS_OFFLOAD_ARCH", "gfx950")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")

@@ -61,6 +61,10 @@ static_assert(kCapGather >= 3 * (int)ZS_MAX_LINE, "a pre-processed line must fit
 static_assert(kCapGather >= (int)ZS_MAX_LINE + 1 + 16, "a raw line must fit");
 constexpr uint64_t kAbsBad = 1ull << 63;  // ABS flag (binned mode): the line's framing is bad
 
+// What a compression launch writes: compressed lines, or only the lines with
+// their rings relabelled - by the pre-processing rule (Sec. IV-A) or by the
+// post-processing rule (zs_postprocess).
+constexpr int kModeCompress = 0, kModePre = 1, kModePost = 2;
 constexpr uint8_t kSkip = 0x7F;    // marker: byte dropped by pre-processing
 constexpr uint8_t kIdMark = 0x80;  // marker: ring-label with ID (low 7 bits)
 constexpr uint32_t kBadLine = 0x8000u;  // LENS flag: the line is bad (empty output)
@@ -152,11 +156,16 @@ __device__ inline void restore_line(uint8_t* raw, uint32_t R, const uint8_t* src
 // Ring IDs of one line with tables in global memory (any number of rings and
 // IDs): the rule of Sec. IV-A written as "latest close per ID": a closing ring
 // takes the smallest ID whose latest closing label precedes its opening label.
-// Markers are written over the raw line.  Returns false if the line is
-// malformed (the raw bytes are then partly overwritten and must be restored).
+// post: the post-processing rule instead - an opening ring takes the smallest
+// label >= 1 not held by an open ring (last[v] then holds the label of the
+// open ring of value v).  Markers are written over the raw line.  Returns
+// false if the line is malformed or needs an ID of 100 or more (the raw bytes
+// are then partly overwritten and must be restored).
+template <bool post>
 __device__ inline bool ring_general(uint8_t* raw, uint32_t R, uint32_t len, uint16_t* open, uint16_t* last,
                                     int* delta) {
     for (int k = 0; k < 100; k++) { open[k] = 0; last[k] = 0; }
+    uint64_t held0 = 1, held1 = 0;  // post: labels held by open rings (label 0 is never used)
     int dl = 0, opens = 0;
     uint32_t inbr = 0;
     for (uint32_t i = 0; i < len; i++) {
@@ -172,14 +181,28 @@ __device__ inline bool ring_general(uint8_t* raw, uint32_t R, uint32_t len, uint
         if (e == 0) {
             open[v] = (uint16_t)(i + 1);
             opens++;
+            if constexpr (post) {
+                uint32_t l = 1;
+                while (l < 100 && ((l < 64 ? held0 >> l : held1 >> (l - 64)) & 1u)) l++;
+                if (l >= 100) return false;
+                if (l < 64) held0 |= 1ull << l;
+                else held1 |= 1ull << (l - 64);
+                last[v] = (uint16_t)l;
+            }
         } else {
             const uint32_t o = e - 1;
             open[v] = 0;
             opens--;
             uint32_t id = 0;
-            while (id < 100 && (uint32_t)last[id] > o + 1) id++;
-            if (id >= 100) return false;
-            last[id] = (uint16_t)(i + 1);
+            if constexpr (post) {
+                id = last[v];
+                if (id < 64) held0 &= ~(1ull << id);
+                else held1 &= ~(1ull << (id - 64));
+            } else {
+                while (id < 100 && (uint32_t)last[id] > o + 1) id++;
+                if (id >= 100) return false;
+                last[id] = (uint16_t)(i + 1);
+            }
             const uint32_t to = (raw[R + o] == '%') ? 3u : 1u;
             raw[R + o] = (uint8_t)(kIdMark | id);
             if (to == 3) raw[R + o + 1] = raw[R + o + 2] = kSkip;
@@ -194,7 +217,7 @@ __device__ inline bool ring_general(uint8_t* raw, uint32_t R, uint32_t len, uint
     return opens == 0;
 }
 
-template <int LK, int CAP>
+template <int LK, int CAP, int MODE>
 struct Compressor {
     static constexpr int kRawCap = CAP, kPreCap = CAP, kSlotBytes = CAP;
     const CompressArgs A;
@@ -211,13 +234,20 @@ struct Compressor {
     __device__ Compressor(const CompressArgs& a, uint8_t* s) : A(a), smem(s) {
         L = compress_lds(a.tab_bytes, CAP);
         H = (const TableHeader*)smem;
-        LENT = smem + H->off_len;
-        COL = smem + H->off_col;
-        TRANS = (const uint16_t*)(smem + H->off_trans);
-        OUTK = (const uint32_t*)(smem + H->off_outk);
-        off_code1 = H->off_code1;
-        off_code = H->off_code;
-        C = H->ncols;
+        if constexpr (MODE == kModeCompress) {
+            LENT = smem + H->off_len;
+            COL = smem + H->off_col;
+            TRANS = (const uint16_t*)(smem + H->off_trans);
+            OUTK = (const uint32_t*)(smem + H->off_outk);
+            off_code1 = H->off_code1;
+            off_code = H->off_code;
+            C = H->ncols;
+        } else {  // pre-processing only: no dictionary staged, none read
+            LENT = COL = nullptr;
+            TRANS = nullptr;
+            OUTK = nullptr;
+            off_code1 = off_code = C = 0;
+        }
     }
 
     __device__ __forceinline__ uint64_t* OFF() { return (uint64_t*)(smem + L.off); }
@@ -332,10 +362,12 @@ struct Compressor {
     // Ring IDs from the label list with a register table of NS open rings
     // (found by label value, free slots reused) and, per open ring, the bit set
     // of the IDs of the rings that closed inside it; a closing ring takes the
-    // smallest ID not in its set (Sec. IV-A).  Markers are written over the
-    // raw line.  Sets *overflow when more than NS rings are open at once or
-    // an ID reaches 32; returns false when rings stay open.
-    template <int NS>
+    // smallest ID not in its set (Sec. IV-A).  post: the post-processing rule
+    // instead - an opening ring takes the smallest label >= 1 not held by an
+    // open ring, kept in the ring's word of the set table.  Markers are written
+    // over the raw line.  Sets *overflow when more than NS rings are open at
+    // once or an ID reaches 32; returns false when rings stay open.
+    template <int NS, bool post>
     __device__ __forceinline__ bool ring_fast(uint8_t* raw, uint32_t R, const uint16_t* list, uint32_t nlab, uint32_t maxlab,
                               int* delta, bool* overflow, bool* marked) {
         // slot word of an open ring: (position + 1) << 8 | ('%' label) << 7 | label
@@ -343,6 +375,7 @@ struct Compressor {
         uint32_t os[NS], mk[NS];
 #pragma unroll
         for (int k = 0; k < NS; k++) { os[k] = 0; mk[k] = 0; }
+        uint32_t held = 1u;  // post: labels held by open rings (label 0 is never used)
         int dl = 0, opens = 0;
         bool ovf = false;
         uint32_t nxt = list[0];
@@ -379,23 +412,27 @@ struct Compressor {
                 if (slot == NS) {
                     ovf = true;  // more than NS rings open
                 } else if (e == 0) {
+                    // post: the opening takes the smallest free label (at most NS are held)
+                    const uint32_t nl = post ? (uint32_t)__builtin_ctz(~held) : 0u;
+                    held |= post ? (1u << nl) : 0u;
 #pragma unroll
                     for (int k = 0; k < NS; k++) {
                         os[k] = (slot == (uint32_t)k) ? (((p + 1) << 8) | (tl == 3 ? 0x80u : 0u) | v) : os[k];
-                        mk[k] = (slot == (uint32_t)k) ? 0u : mk[k];
+                        mk[k] = (slot == (uint32_t)k) ? nl : mk[k];
                     }
                     opens++;
                 } else if ((e & 0x7Fu) == v) {
                     const uint32_t o = (e >> 8) - 1;
-                    const uint32_t id = (uint32_t)__builtin_ctz(~m);
-                    if (m == 0xFFFFFFFFu) {
+                    const uint32_t id = post ? m : (uint32_t)__builtin_ctz(~m);
+                    if (!post && m == 0xFFFFFFFFu) {
                         ovf = true;
                     } else {
                         const uint32_t bit = 1u << id;
+                        held &= post ? ~bit : ~0u;
 #pragma unroll
                         for (int k = 0; k < NS; k++) {
                             os[k] = (slot == (uint32_t)k) ? 0u : os[k];
-                            mk[k] |= bit;
+                            mk[k] |= post ? 0u : bit;
                         }
                         opens--;
                         const uint32_t to = (e & 0x80u) ? 3u : 1u;
@@ -628,14 +665,15 @@ struct Compressor {
 #pragma unroll
             for (int d = 32; d >= 1; d >>= 1) maxlab = max(maxlab, (uint32_t)__shfl_xor((int)maxlab, d, 64));
             bool marked = false;
+            constexpr bool post = MODE == kModePost;
             if (run_rings) {
                 // a table of 4 slots first (more rings than that are rarely open at
                 // once), 8 for the lines it cannot hold
-                bool ok = ring_fast<kSlotsFirst>(raw, st.R, list, nlab, maxlab, &delta, &overflow, &marked);
+                bool ok = ring_fast<kSlotsFirst, post>(raw, st.R, list, nlab, maxlab, &delta, &overflow, &marked);
                 if (overflow) {
                     restore_line(raw, st.R, line_src(line), st.len);
                     overflow = false;
-                    ok = ring_fast<kSlots>(raw, st.R, list, nlab, maxlab, &delta, &overflow, &marked);
+                    ok = ring_fast<kSlots, post>(raw, st.R, list, nlab, maxlab, &delta, &overflow, &marked);
                 }
                 if (!ok && !overflow) {
                     malformed = true;
@@ -645,7 +683,7 @@ struct Compressor {
             if (overflow) {
                 restore_line(raw, st.R, line_src(line), st.len);
                 uint16_t* open = (uint16_t*)(A.gen + ((uint64_t)blockIdx.x * kWG + tid) * kGenLane);
-                if (!ring_general(raw, st.R, st.len, open, open + 100, &delta)) {
+                if (!ring_general<post>(raw, st.R, st.len, open, open + 100, &delta)) {
                     malformed = true;
                     restore_line(raw, st.R, line_src(line), st.len);
                 } else {
@@ -700,7 +738,10 @@ struct Compressor {
         // ---- parse (backward): automaton + (min,+) window over the next LK costs
         uint32_t cost = 0;
         bool esc_any = false;
-        {
+        constexpr bool preonly = MODE != kModeCompress;
+        if constexpr (preonly) {
+            cost = (st.in && !st.bad) ? st.m : 0u;  // the output line is the relabelled line
+        } else {
             uint8_t* buf = st.simple ? raw : pre;
             const uint32_t m = (st.in && !st.bad) ? st.m : 0u;
             uint32_t mx = m;
@@ -736,7 +777,7 @@ struct Compressor {
         }
         // a compressed line longer than the decoder takes is bad, like a raw line
         // longer than ZS_MAX_LINE (only renumbering that lengthens a line can get there)
-        if (st.in && !st.bad && cost > ZS_MAX_CLINE) {
+        if (!preonly && st.in && !st.bad && cost > ZS_MAX_CLINE) {
             st.bad = true;
             note_error(A.ws, line_id(k0, b0 + st.j), kErrInval);
         }
@@ -764,7 +805,16 @@ struct Compressor {
             // (codes, escapes, newline) with dword stores
             const uintptr_t a0 = rel ? 0 : (((uintptr_t)(A.out + gb0)) & ~(uintptr_t)15);
             const uintptr_t sbase = rel ? 0 : (uintptr_t)A.out - a0;
-            if (st.in && !st.esc) {
+            if constexpr (MODE != kModeCompress) {
+                // relabelling only: the line's bytes and its newline
+                if (st.in) {
+                    StageWriter wr;
+                    wr.begin(stage, (uint32_t)(sbase + oc));
+                    for (; ic < m; ic++) wr.add(pre[st.P + ic], 1);
+                    wr.add('\n', 1);
+                    wr.finish();
+                }
+            } else if (st.in && !st.esc) {
                 // one byte per code: a 32-bit accumulator, dword stores, bytes
                 // only in the dwords shared with the neighbouring lines
                 uint32_t* st32 = (uint32_t*)stage;
@@ -831,7 +881,7 @@ struct Compressor {
                     } else {
                         b[0] = t;
                         tl = 1;
-                        adv = LENT[t];
+                        adv = MODE != kModeCompress ? 1u : LENT[t];
                     }
                 } else {
                     b[0] = '\n';
@@ -1008,7 +1058,7 @@ struct Compressor {
     }
 };
 
-template <int LK, int CAP>
+template <int LK, int CAP, int MODE = kModeCompress>
 __global__ void __launch_bounds__(kWG) compress_kernel(CompressArgs a) {
     extern __shared__ __align__(16) uint8_t smem[];
     // stage the dictionary image (up to EXP) in LDS
@@ -1019,7 +1069,7 @@ __global__ void __launch_bounds__(kWG) compress_kernel(CompressArgs a) {
         smem[compress_lds(a.tab_bytes, CAP).ident + threadIdx.x] = (uint8_t)threadIdx.x;
     }
     __syncthreads();
-    Compressor<LK, CAP> c(a, smem);
+    Compressor<LK, CAP, MODE> c(a, smem);
     c.run();
 }
 
@@ -2608,16 +2658,19 @@ static zs_status launch_init(WsHeader* h, uint64_t* status, uint32_t ntiles, Res
 }
 
 // One compression launch: the persistent grid of the LDS variant, at most
-// max_tiles workgroups.
-static zs_status launch_compress(const zs_dict* d, const CompressArgs& a, bool large, uint32_t max_tiles, int cus,
-                                 hipStream_t s) {
+// max_tiles workgroups.  tab_bytes: dictionary image staged (0: none, for
+// pre-processing only); lk: the parse window of the dictionary (8 or 16).
+static zs_status launch_compress(uint32_t tab_bytes, uint32_t lk, const CompressArgs& a, bool large,
+                                 uint32_t max_tiles, int cus, hipStream_t s, int mode = kModeCompress) {
     // plain: kCapSmall; binned: kCapGather, or kCapLarge for the bins that ask for it
     const int cap = large ? kCapLarge : (a.ids ? kCapGather : kCapSmall);
-    const CompressLds cl = compress_lds(d->comp_bytes, cap);
+    const CompressLds cl = compress_lds(tab_bytes, cap);
     const uint32_t lds = a.ids ? cl.total_gather : cl.total;
-    const bool k8 = d->lk == 8;
-    const void* kfn = cap == kCapLarge   ? (k8 ? (const void*)compress_kernel<8, kCapLarge>
-                                              : (const void*)compress_kernel<16, kCapLarge>)
+    const bool k8 = lk == 8;
+    const void* kfn = mode == kModePre    ? (const void*)compress_kernel<8, kCapSmall, kModePre>
+                      : mode == kModePost ? (const void*)compress_kernel<8, kCapSmall, kModePost>
+                      : cap == kCapLarge  ? (k8 ? (const void*)compress_kernel<8, kCapLarge>
+                                                : (const void*)compress_kernel<16, kCapLarge>)
                       : cap == kCapGather ? (k8 ? (const void*)compress_kernel<8, kCapGather>
                                                 : (const void*)compress_kernel<16, kCapGather>)
                                           : (k8 ? (const void*)compress_kernel<8, kCapSmall>
@@ -2632,13 +2685,11 @@ static zs_status launch_compress(const zs_dict* d, const CompressArgs& a, bool l
     return ZS_OK;
 }
 
-zs_status zs_compress(const zs_dict* d, const uint8_t* in, uint64_t in_bytes, const uint64_t* in_off,
-                      uint64_t n_lines, uint8_t* out, uint64_t out_cap, uint64_t* out_off, uint32_t flags,
-                      void* ws, size_t ws_bytes, zs_result* res, void* stream) {
-    if (!d || !in_off || !out_off || !ws || (!in && in_bytes)) return ZS_EINVAL;
-    if (ws_bytes < zs_workspace_bytes(ZS_OP_COMPRESS, n_lines)) return ZS_EINVAL;
-    if (flags & ~ZS_F_PREPROCESS) return ZS_EINVAL;
-    hipStream_t s = (hipStream_t)stream;
+// Plain (one launch) compression; with d null, the ring relabelling alone
+// (mode: pre- or post-processing).
+static zs_status compress_plain(const zs_dict* d, const uint8_t* in, uint64_t in_bytes, const uint64_t* in_off,
+                                uint64_t n_lines, uint8_t* out, uint64_t out_cap, uint64_t* out_off, uint32_t flags,
+                                void* ws, zs_result* res, hipStream_t s, int mode = kModeCompress) {
     if (n_lines == 0) {
         hipLaunchKernelGGL(empty_result_kernel, dim3(1), dim3(1), 0, s, out_off, (ResultOut*)res);
         return hipGetLastError() == hipSuccess ? ZS_OK : ZS_EDEVICE;
@@ -2653,8 +2704,8 @@ zs_status zs_compress(const zs_dict* d, const uint8_t* in, uint64_t in_bytes, co
     uint8_t* slots = gen + compress_grid_cap(n_lines, di.cus) * kWG * kGenLane;
     if (launch_init(h, status, ntiles, (ResultOut*)res, s) != ZS_OK) return ZS_EDEVICE;
     CompressArgs a;
-    a.tables = d->d_tables;
-    a.tab_bytes = d->comp_bytes;
+    a.tables = d ? d->d_tables : nullptr;
+    a.tab_bytes = d ? d->comp_bytes : 0u;
     a.in = in;
     a.in_bytes = in_bytes;
     a.in_off = in_off;
@@ -2673,7 +2724,35 @@ zs_status zs_compress(const zs_dict* d, const uint8_t* in, uint64_t in_bytes, co
     a.plan = nullptr;
     a.bin_lo = a.bin_hi = 0;
     a.ticket = nullptr;
-    return launch_compress(d, a, false, ntiles, di.cus, s);
+    return launch_compress(a.tab_bytes, d ? d->lk : 8u, a, false, ntiles, di.cus, s, mode);
+}
+
+zs_status zs_compress(const zs_dict* d, const uint8_t* in, uint64_t in_bytes, const uint64_t* in_off,
+                      uint64_t n_lines, uint8_t* out, uint64_t out_cap, uint64_t* out_off, uint32_t flags,
+                      void* ws, size_t ws_bytes, zs_result* res, void* stream) {
+    if (!d || !in_off || !out_off || !ws || (!in && in_bytes)) return ZS_EINVAL;
+    if (ws_bytes < zs_workspace_bytes(ZS_OP_COMPRESS, n_lines)) return ZS_EINVAL;
+    if (flags & ~ZS_F_PREPROCESS) return ZS_EINVAL;
+    return compress_plain(d, in, in_bytes, in_off, n_lines, out, out_cap, out_off, flags, ws, res,
+                          (hipStream_t)stream);
+}
+
+zs_status zs_preprocess(const uint8_t* in, uint64_t in_bytes, const uint64_t* in_off, uint64_t n_lines,
+                        uint8_t* out, uint64_t out_cap, uint64_t* out_off, void* ws, size_t ws_bytes,
+                        zs_result* res, void* stream) {
+    if (!in_off || !out_off || !ws || (!in && in_bytes)) return ZS_EINVAL;
+    if (ws_bytes < zs_workspace_bytes(ZS_OP_COMPRESS, n_lines)) return ZS_EINVAL;
+    return compress_plain(nullptr, in, in_bytes, in_off, n_lines, out, out_cap, out_off, ZS_F_PREPROCESS, ws, res,
+                          (hipStream_t)stream, kModePre);
+}
+
+zs_status zs_postprocess(const uint8_t* in, uint64_t in_bytes, const uint64_t* in_off, uint64_t n_lines,
+                         uint8_t* out, uint64_t out_cap, uint64_t* out_off, void* ws, size_t ws_bytes,
+                         zs_result* res, void* stream) {
+    if (!in_off || !out_off || !ws || (!in && in_bytes)) return ZS_EINVAL;
+    if (ws_bytes < zs_workspace_bytes(ZS_OP_COMPRESS, n_lines)) return ZS_EINVAL;
+    return compress_plain(nullptr, in, in_bytes, in_off, n_lines, out, out_cap, out_off, ZS_F_PREPROCESS, ws, res,
+                          (hipStream_t)stream, kModePost);
 }
 
 
@@ -2764,7 +2843,8 @@ zs_status zs_compress_binned(const zs_dict* d, const uint8_t* in, uint64_t in_by
         // an upper bound of this launch's tiles sizes the grid
         uint64_t most = 0;
         for (uint32_t k = b; k < e; k++) most += (n_lines + bi.lpt[k] - 1) / bi.lpt[k];
-        if (launch_compress(d, a, large[b] != 0, (uint32_t)std::min<uint64_t>(most, w.max_tiles), di.cus, s) != ZS_OK)
+        if (launch_compress(d->comp_bytes, d->lk, a, large[b] != 0, (uint32_t)std::min<uint64_t>(most, w.max_tiles),
+                            di.cus, s) != ZS_OK)
             return ZS_EDEVICE;
         b = e;
         launch++;
