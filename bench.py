@@ -56,6 +56,7 @@ def parse():
     ap.add_argument("--serve-gb", type=float, default=50.0, help="compressed shard bytes resident (GB)")
     ap.add_argument("--shard-lines", type=int, default=40_000_000)
     ap.add_argument("--slots", type=int, default=16)
+    ap.add_argument("--serve-plain", type=int, default=1000, help="requests replayed through the plain calls")
     ap.add_argument("--probe-copy", action="store_true",
                     help="after the timed steps, one plain 1 GiB device copy (scales the HBM byte counters)")
     ap.add_argument("--tune-lines", type=int, default=1_000_000, help="sample the autotuner times (uneven)")
@@ -449,9 +450,6 @@ def bench_serve(args):
             return srv.submit_decompress(sids[r[1]], r[2])
         return srv.submit_compress(r[3], r[4])
 
-    def user_bytes(r, data):
-        return data.size if r[0] == "d" else r[3].size
-
     # closed loop: capacity
     ncl = max(2, 2 * args.slots)
     per = max(20, args.serve_requests // (5 * ncl))
@@ -461,8 +459,8 @@ def bench_serve(args):
         rng = np.random.default_rng(1000 + i)
         for _ in range(per):
             r = make(rng)
-            code, fb, data, offs, t = srv.wait(submit(r))
-            done_bytes[i] += user_bytes(r, data)
+            code, fb, data, offs, t = srv.wait(submit(r), copy=False)
+            done_bytes[i] += t["bytes"] if r[0] == "d" else r[3].size
 
     log("closed loop: %d clients x %d requests" % (ncl, per))
     t0 = time.perf_counter()
@@ -481,6 +479,9 @@ def bench_serve(args):
     rreq = np.random.default_rng(55)
     reqs = [make(rreq) for _ in range(nreq)]
     lat = np.zeros(nreq)
+    sublag = np.zeros(nreq)  # scheduled arrival -> submission returned (the submitting thread)
+    qlat = np.zeros(nreq)  # arrival -> admission (queueing)
+    slat = np.zeros(nreq)  # admission -> completion (service: sizing, call, copies)
     kinds = np.array([r[0] == "d" for r in reqs])
     ubytes = np.zeros(nreq)
     replies = {}
@@ -496,10 +497,14 @@ def bench_serve(args):
             next_wait[0] += 1
             if i >= nreq:
                 return
-            code, fb, data, offs, t = srv.wait(tickets[i])
+            keep = i in verify
+            code, fb, data, offs, t = srv.wait(tickets[i], copy=keep)
             lat[i] = t["done"] - arrive[i]
-            ubytes[i] = user_bytes(reqs[i], data)
-            if i in verify or code != 0:
+            sublag[i] = t["submit"] - arrive[i]
+            qlat[i] = t["admit"] - arrive[i]
+            slat[i] = t["done"] - t["admit"]
+            ubytes[i] = t["bytes"] if reqs[i][0] == "d" else reqs[i][3].size
+            if keep or code != 0:
                 replies[i] = (code, fb, data, offs)
 
     next_wait = [0]
@@ -521,6 +526,23 @@ def bench_serve(args):
     span = max(time.monotonic() - base, 1e-9)
     st = srv.stats()
     srv.close()
+    # the same requests through the plain per-launch calls, one at a time on one stream
+    # (inputs to the device, size-only pass, the call, results to the host), no request loop
+    nplain = min(nreq, args.serve_plain)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    pbytes = 0
+    for r in reqs[:nplain]:
+        if r[0] == "d":
+            sc, sco = shards[r[1]]
+            data, offs = zs.decompress_lines(d, sc, sco, torch.from_numpy(r[2].astype(np.int64)).to(dev),
+                                             check=False)
+        else:
+            data, offs = zs.compress(d, torch.from_numpy(r[3]).to(dev),
+                                     torch.from_numpy(r[4].astype(np.int64)).to(dev), check=False)
+        hd, ho = data.cpu().numpy(), offs.cpu().numpy()
+        pbytes += hd.size if r[0] == "d" else r[3].size
+    plain_s = time.perf_counter() - t0
     # verification of a sample against the oracle
     od = oracle.Dict.load(zs.default_dict_path())
     checked = bad = 0
@@ -560,7 +582,20 @@ def bench_serve(args):
                     "latency_ms": {"p50": p(lat, 50), "p99": p(lat, 99),
                                    "random_access_p50": p(lat[kinds], 50), "random_access_p99": p(lat[kinds], 99),
                                    "compress_p50": p(lat[~kinds], 50), "compress_p99": p(lat[~kinds], 99)},
+                    "submit_lag_ms": {"p50": p(sublag, 50), "p99": p(sublag, 99)},
+                    "queue_ms": {"p50": p(qlat, 50), "p99": p(qlat, 99)},
+                    "service_ms": {"p50": p(slat, 50), "p99": p(slat, 99),
+                                   "random_access_p50": p(slat[kinds], 50), "random_access_p99": p(slat[kinds], 99),
+                                   "compress_p50": p(slat[~kinds], 50), "compress_p99": p(slat[~kinds], 99)},
                     "user_GBs": round(float(ubytes.sum()) / span / 1e9, 3),
+                    "plain_calls": {"requests": nplain, "seconds": round(plain_s, 3),
+                                    "req_s": round(nplain / plain_s, 2) if plain_s else None,
+                                    "user_GBs": round(pbytes / plain_s / 1e9, 3) if plain_s else None,
+                                    "served_capacity_vs_plain": round(capacity / (nplain / plain_s), 2)
+                                    if plain_s else None,
+                                    "what": "the first requests of the open-loop sequence through the plain calls "
+                                            "(compress / decompress_lines with a size-only pass, results copied "
+                                            "to the host), one at a time on one stream"},
                     "resident_GB": round(resident / 1e9, 2),
                     "verified": {"checked": checked, "mismatches": bad, "sample": "random requests, compression "
                                  "requests of at most 20,000 lines, against the oracle"},

@@ -194,8 +194,11 @@ typedef struct {
     uint32_t edges[ZS_MAX_BINS - 1];       /* ascending raw-length bounds: bin i holds lengths in */
                                            /* [edges[i-1], edges[i]) (edges[-1] = 0, last open)   */
     uint32_t lines_per_tile[ZS_MAX_BINS];  /* per bin, 32..256: lines (lanes) per workgroup tile  */
-    uint32_t large_lds[ZS_MAX_BINS];       /* per bin, 0 or 1: the LDS layout with the larger     */
-                                           /* line batch (2 workgroups per CU instead of 3)       */
+    uint32_t large_lds[ZS_MAX_BINS];       /* per bin, where a tile's lines are held: 0 LDS (3    */
+                                           /* workgroups per CU), 1 a larger LDS batch (2 per     */
+                                           /* CU), 2 global memory (the workspace: up to 256 KiB  */
+                                           /* of lines per tile, so a tile of long lines keeps    */
+                                           /* every lane busy; LDS then holds the automaton)      */
 } zs_bin_config;
 
 size_t zs_binned_workspace_bytes(uint64_t n_lines, uint64_t out_cap);

@@ -47,7 +47,8 @@ MAX_BINS = 8
 
 
 class BinConfig(ctypes.Structure):
-    """zs_bin_config: bins by raw line length (ascending edges), lines per tile and LDS layout per bin."""
+    """zs_bin_config: bins by raw line length (ascending edges), lines per tile and line-buffer layout
+    per bin (large_lds: 0 LDS, 1 larger LDS batch, 2 line buffers in global memory)."""
     _fields_ = [("nbins", ctypes.c_uint32), ("edges", ctypes.c_uint32 * (MAX_BINS - 1)),
                 ("lines_per_tile", ctypes.c_uint32 * MAX_BINS), ("large_lds", ctypes.c_uint32 * MAX_BINS)]
 
@@ -628,15 +629,20 @@ class Server:
                   "zs_server_submit_compress")
         return int(t.value)
 
-    def wait(self, ticket):
+    def wait(self, ticket, copy=True):
+        """Block until the request is done; (code, first_bad, data, offsets, times).  With
+        copy=False the reply's bytes and offsets are not copied out (empty arrays; the byte
+        count is in times["bytes"])."""
         r = Reply()
         _check_rc(lib().zs_server_wait(self.handle, ticket, ctypes.byref(r)), "zs_server_wait")
         n = int(r.n)
         # a request that failed before its output was written has no offsets
-        off = np.ctypeslib.as_array(r.off, shape=(n + 1,)).copy() if r.off else np.zeros(0, dtype=np.uint64)
-        data = np.ctypeslib.as_array(r.data, shape=(int(r.bytes),)).copy() if r.bytes else \
+        off = np.ctypeslib.as_array(r.off, shape=(n + 1,)).copy() if (r.off and copy) else \
+            np.zeros(0, dtype=np.uint64)
+        data = np.ctypeslib.as_array(r.data, shape=(int(r.bytes),)).copy() if (r.bytes and copy) else \
             np.zeros(0, dtype=np.uint8)
-        t = {"submit": r.t_submit, "admit": r.t_admit, "done": r.t_done, "footprint": int(r.footprint)}
+        t = {"submit": r.t_submit, "admit": r.t_admit, "done": r.t_done, "footprint": int(r.footprint),
+             "bytes": int(r.bytes)}
         code, fb = int(r.code), int(r.first_bad)
         lib().zs_server_release(self.handle, ticket)
         return code, fb, data, off, t

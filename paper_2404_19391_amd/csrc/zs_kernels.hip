@@ -53,8 +53,14 @@ constexpr int kCL = 256;              // lines per tile at most (one per thread)
 constexpr int kCapSmall = 14336;
 constexpr int kCapGather = 13312;  // binned short bins: room for the ABS array at 3 workgroups per CU
 constexpr int kCapLarge = 26624;
+// Global-memory layout (long-line bins): the line buffers of a workgroup live in
+// its own region of the workspace, so LDS holds only the automaton and the
+// per-line arrays and a tile of 256 long lines keeps every lane busy.
+constexpr int kCapGlobal = 262144;
+constexpr size_t kGlStride = 2 * (size_t)kCapGlobal + kCapGlobal / 8 + 256;  // RAW, PRE, ESC bits, margins
 constexpr int kSlots = 8;             // fast ring table (registers): up to 8 open rings, found by label
 constexpr int kSlotsFirst = 4;        // the smaller table tried first
+constexpr int kSlotsLong = 16;        // the table of the global-memory layout (long lines)
 constexpr int kGenLane = 400;         // per-lane ring tables in global memory (any line):
                                       // 100 open positions u16 + 100 last-close u16
 static_assert(kCapGather >= 3 * (int)ZS_MAX_LINE, "a pre-processed line must fit");
@@ -76,13 +82,14 @@ struct CompressLds {
     uint32_t total_gather;  // binned mode (ABS at the end)
 };
 
-__host__ __device__ inline CompressLds compress_lds(uint32_t tab_bytes, uint32_t cap) {
+__host__ __device__ inline CompressLds compress_lds(uint32_t tab_bytes, uint32_t cap, bool gl = false) {
     CompressLds L;
     L.tab_bytes = align16(tab_bytes);
     uint32_t o = L.tab_bytes;
-    L.raw = o;  o += cap;
-    L.pre = o;  o += cap;
-    L.esc = o;  o += cap / 8;
+    const uint32_t lds_cap = gl ? 0u : cap;  // gl: RAW, PRE and ESC are in global memory
+    L.raw = o;  o += lds_cap;
+    L.pre = o;  o += lds_cap;
+    L.esc = o;  o += lds_cap / 8;
     L.off = o;  o += align16((kCL + 1) * 8);
     L.cost = o; o += kCL * 4;
     L.eoff = o; o += kCL * 4;
@@ -132,6 +139,7 @@ struct CompressArgs {
     const struct BinPlan* plan;
     uint32_t bin_lo, bin_hi;  // the bins this launch takes
     uint32_t* ticket;       // this launch's tile counter
+    uint8_t* glines;        // global-memory layout: kGlStride bytes per workgroup
 };
 
 __device__ inline bool is_digit(uint32_t c) { return c - '0' < 10u; }
@@ -217,12 +225,15 @@ __device__ inline bool ring_general(uint8_t* raw, uint32_t R, uint32_t len, uint
     return opens == 0;
 }
 
-template <int LK, int CAP, int MODE>
+template <int LK, int CAP, int MODE, bool GL = false>
 struct Compressor {
     static constexpr int kRawCap = CAP, kPreCap = CAP, kSlotBytes = CAP;
     const CompressArgs A;
     uint8_t* smem;
     CompressLds L;
+    uint8_t* g_raw = nullptr;  // GL: this workgroup's line buffers in global memory
+    uint8_t* g_pre = nullptr;
+    uint32_t* g_esc = nullptr;
     const TableHeader* H;
     const uint8_t* LENT;  // expansion lengths
     const uint8_t* COL;
@@ -232,7 +243,13 @@ struct Compressor {
     uint32_t C;  // automaton columns
 
     __device__ Compressor(const CompressArgs& a, uint8_t* s) : A(a), smem(s) {
-        L = compress_lds(a.tab_bytes, CAP);
+        L = compress_lds(a.tab_bytes, CAP, GL);
+        if constexpr (GL) {
+            uint8_t* b = a.glines + (uint64_t)blockIdx.x * kGlStride + 128;
+            g_raw = b;
+            g_pre = b + CAP;
+            g_esc = (uint32_t*)(b + 2 * (size_t)CAP);
+        }
         H = (const TableHeader*)smem;
         if constexpr (MODE == kModeCompress) {
             LENT = smem + H->off_len;
@@ -257,9 +274,33 @@ struct Compressor {
     __device__ __forceinline__ uint16_t* LENS() { return (uint16_t*)(smem + L.lens); }
     __device__ __forceinline__ uint16_t* PERM() { return (uint16_t*)(smem + L.perm); }
     __device__ __forceinline__ uint32_t* MISC() { return (uint32_t*)(smem + L.misc); }
-    __device__ __forceinline__ uint8_t* RAW() { return smem + L.raw; }
-    __device__ __forceinline__ uint8_t* PRE() { return smem + L.pre; }
-    __device__ __forceinline__ uint32_t* ESC() { return (uint32_t*)(smem + L.esc); }
+    __device__ __forceinline__ uint8_t* RAW() {
+        if constexpr (GL) return g_raw;
+        else return smem + L.raw;
+    }
+    __device__ __forceinline__ uint8_t* PRE() {
+        if constexpr (GL) return g_pre;
+        else return smem + L.pre;
+    }
+    __device__ __forceinline__ uint32_t* ESC() {
+        if constexpr (GL) return g_esc;
+        else return (uint32_t*)(smem + L.esc);
+    }
+    // Workgroup barrier.  GL: a barrier does not wait for a wave's global stores,
+    // and the line buffers are written by one wave and read by another, so
+    // every wave first waits for its own memory operations to complete.
+    __device__ __forceinline__ void bar() {
+        if constexpr (GL) __builtin_amdgcn_s_waitcnt(0);
+        __syncthreads();
+    }
+    __device__ __forceinline__ bool bar_or(bool v) {
+        if constexpr (GL) __builtin_amdgcn_s_waitcnt(0);
+        return __syncthreads_or(v) != 0;
+    }
+    __device__ __forceinline__ bool bar_and(bool v) {
+        if constexpr (GL) __builtin_amdgcn_s_waitcnt(0);
+        return __syncthreads_and(v) != 0;
+    }
 
     // Index of line j of the tile in the input (binned mode: from the id list).
     __device__ __forceinline__ uint64_t line_id(uint64_t k0, uint32_t j) { return A.ids ? A.ids[k0 + j] : k0 + j; }
@@ -469,10 +510,52 @@ struct Compressor {
     // stepping on bytes at or just before its line start, but stores into its
     // sink byte and keeps its costs, so that the group is one block the
     // scheduler can interleave.  Escapes are collected in *escm.
+    // GL: the bytes a step group reads two places back, [lo, lo + LK), loaded one
+    // group ahead (byte lo + j in bits 8j of w[j / 8])
+    struct Win {
+        uint64_t w[LK / 8];
+    };
+    __device__ __forceinline__ Win load_win(const uint8_t* buf, int32_t lo) {
+        const uintptr_t ad = (uintptr_t)(buf + lo);
+        const uint64_t* a = (const uint64_t*)(ad & ~(uintptr_t)7);
+        const uint32_t sh = 8u * (uint32_t)(ad & 7);
+        uint64_t v[LK / 8 + 1];
+#pragma unroll
+        for (int j = 0; j <= LK / 8; j++) v[j] = a[j];
+        Win r;
+#pragma unroll
+        for (int j = 0; j < LK / 8; j++) r.w[j] = sh ? (v[j] >> sh) | (v[j + 1] << (64 - sh)) : v[j];
+        return r;
+    }
+
+    // GL: a forward reader of one lane's bytes in global memory, 16 bytes at a
+    // time with the next 16 already loaded, so that a walk whose next address
+    // depends on the byte just read does not wait for memory at every byte.
+    struct TokWin {
+        uintptr_t wa = 0;  // address of the 16 bytes in cw
+        uint4 cw, nw;
+        __device__ __forceinline__ void init(const uint8_t* p) {
+            wa = (uintptr_t)p & ~(uintptr_t)15;
+            cw = *(const uint4*)wa;
+            nw = *(const uint4*)(wa + 16);
+        }
+        __device__ __forceinline__ uint32_t get(const uint8_t* p) {
+            const uintptr_t ad = (uintptr_t)p;
+            while (ad >= wa + 16) {
+                cw = nw;
+                wa += 16;
+                nw = *(const uint4*)(wa + 16);
+            }
+            const uint32_t i = (uint32_t)(ad - wa);
+            const uint32_t w = i < 8 ? (i < 4 ? cw.x : cw.y) : (i < 12 ? cw.z : cw.w);
+            return (w >> (8 * (i & 3))) & 0xFFu;
+        }
+    };
+
     template <int K>
     __device__ __forceinline__ void parse_steps(ParseState& ps, uint8_t* buf, uint32_t base, uint32_t m,
                                                 uint32_t top, int32_t P, uint8_t* sink, uint32_t Cs,
-                                                uint32_t* escm) {
+                                                uint32_t* escm, const Win& win) {
         if constexpr (K < LK) {
             const uint32_t it = base + K;
             const bool act = it < m;
@@ -481,7 +564,12 @@ struct Compressor {
                 const uint32_t s = ps.s;
                 // the next state and the byte two places back are independent of the DP below
                 const uint32_t sn = TRANS[__umul24(s, Cs) + ps.coln];
-                const uint32_t cnn = buf[max(pos, P) - 2];  // may read just before the line: any byte will do
+                uint32_t cnn;
+                if constexpr (GL) {
+                    cnn = (uint32_t)(win.w[(LK - 1 - K) / 8] >> (8 * ((LK - 1 - K) % 8))) & 0xFFu;
+                } else {
+                    cnn = buf[max(pos, P) - 2];  // may read just before the line: any byte will do
+                }
                 const uint32_t colnn = COL[cnn];
                 const uint32_t* ok = OUTK + s * LK;
                 uint32_t Kmin = ps.V[(K + LK - 1) % LK] + 63u;  // escape: cost[i+1] + 2, low bits 31
@@ -504,7 +592,7 @@ struct Compressor {
                 ps.cn = cnn;
                 ps.coln = colnn;
             }
-            parse_steps<K + 1>(ps, buf, base, m, top, P, sink, Cs, escm);
+            parse_steps<K + 1>(ps, buf, base, m, top, P, sink, Cs, escm, win);
         }
     }
 
@@ -541,6 +629,18 @@ struct Compressor {
                     else if (!(a & kAbsBad)) v[k] = A.in[(a & ~kAbsBad) + (r - qs)];
                 }
             }
+            if constexpr (GL) {
+                // global line buffer: whole pieces with one 16-byte store
+                if (r0 + 16 <= n) {
+                    uint32_t w[4];
+#pragma unroll
+                    for (int j = 0; j < 4; j++)
+                        w[j] = v[4 * j] | ((uint32_t)v[4 * j + 1] << 8) | ((uint32_t)v[4 * j + 2] << 16) |
+                               ((uint32_t)v[4 * j + 3] << 24);
+                    *(uint4*)(raw + r0) = make_uint4(w[0], w[1], w[2], w[3]);
+                    continue;
+                }
+            }
 #pragma unroll
             for (int k = 0; k < 16; k++)
                 if (r0 + k < n) raw[r0 + k] = v[k];
@@ -561,7 +661,7 @@ struct Compressor {
         const bool prep = (A.flags & ZS_F_PREPROCESS) != 0;
         // ---- extent of the batch
         if (tid == 0) misc[0] = nl;
-        __syncthreads();
+        bar();
         {
             const uint32_t j = b0 + tid;
             if (j < nl && j > b0) {
@@ -569,10 +669,11 @@ struct Compressor {
                 if (stop) atomicMin(&misc[0], j);
             }
         }
-        __syncthreads();
+        bar();
         uint32_t b1 = misc[0];
-        __syncthreads();
+        bar();
         bool marked_lane = false;
+        uint32_t ext = 0;  // bytes of RAW or PRE the batch uses (GL: the escape bits cleared)
         while (true) {
             const uint32_t nb = b1 - b0;
             // ---- load
@@ -587,11 +688,11 @@ struct Compressor {
                 const uintptr_t a0 = ((uintptr_t)(A.in + lo)) & ~(uintptr_t)15;
                 base_off = (uint32_t)((uintptr_t)(A.in + lo) - a0);
                 if (fe0 == 0) load_range(A.in, A.in_bytes, lo, hi, a0, raw);
-                __syncthreads();
+                bar();
                 if (tid == 0 && fe0 == 0 && off[b1] == A.in_bytes + 1)
                     raw[(uint32_t)(off[b1] - 1 - lo) + base_off] = '\n';
             }
-            __syncthreads();
+            bar();
             // ---- framing per line, lengths for the rank order
             if (tid < nb) {
                 const uint32_t j = b0 + tid;
@@ -604,20 +705,20 @@ struct Compressor {
                 if (fe) note_error(A.ws, line_id(k0, j), fe);
                 lens[tid] = fe ? (uint16_t)kBadLine : (uint16_t)len;
             }
-            __syncthreads();
+            bar();
             // ---- rank lines by length (buckets of 8 bytes) so that a wave holds lines of
             //      similar length; the order inside a bucket does not affect any result
             {
                 uint32_t* cnt = ESC();  // scratch until the escape bits are cleared
                 if (tid < 64) cnt[tid] = 0;
-                __syncthreads();
+                bar();
                 uint32_t bk = 0, within = 0;
                 if (tid < nb) {
                     const uint32_t lj = lens[tid];
                     bk = (lj & kBadLine) ? 0u : min(lj >> 3, 31u);
                     within = atomicAdd(&cnt[bk], 1u);
                 }
-                __syncthreads();
+                bar();
                 if (tid < 32) {
                     const uint32_t v = cnt[tid];
                     uint32_t inc = v;
@@ -628,10 +729,10 @@ struct Compressor {
                     }
                     cnt[32 + tid] = inc - v;
                 }
-                __syncthreads();
+                bar();
                 if (tid < nb) perm[cnt[32 + bk] + within] = (uint16_t)tid;
             }
-            __syncthreads();
+            bar();
             // wave w takes the ((w + rot) mod 4)-th quarter of the length order:
             // the wave with the longest lines moves from tile to tile, so that
             // it does not sit on the same SIMD in every workgroup of the CU
@@ -667,13 +768,19 @@ struct Compressor {
             bool marked = false;
             constexpr bool post = MODE == kModePost;
             if (run_rings) {
-                // a table of 4 slots first (more rings than that are rarely open at
-                // once), 8 for the lines it cannot hold
-                bool ok = ring_fast<kSlotsFirst, post>(raw, st.R, list, nlab, maxlab, &delta, &overflow, &marked);
-                if (overflow) {
-                    restore_line(raw, st.R, line_src(line), st.len);
-                    overflow = false;
-                    ok = ring_fast<kSlots, post>(raw, st.R, list, nlab, maxlab, &delta, &overflow, &marked);
+                bool ok;
+                if constexpr (GL) {
+                    // long lines hold more rings open at once: one table of 16 slots
+                    ok = ring_fast<kSlotsLong, post>(raw, st.R, list, nlab, maxlab, &delta, &overflow, &marked);
+                } else {
+                    // a table of 4 slots first (more rings than that are rarely open at
+                    // once), 8 for the lines it cannot hold
+                    ok = ring_fast<kSlotsFirst, post>(raw, st.R, list, nlab, maxlab, &delta, &overflow, &marked);
+                    if (overflow) {
+                        restore_line(raw, st.R, line_src(line), st.len);
+                        overflow = false;
+                        ok = ring_fast<kSlots, post>(raw, st.R, list, nlab, maxlab, &delta, &overflow, &marked);
+                    }
                 }
                 if (!ok && !overflow) {
                     malformed = true;
@@ -696,19 +803,34 @@ struct Compressor {
             // ---- pack the pre-processed lines (in lane order)
             uint32_t total;
             st.P = block_excl_scan(st.in ? st.m : 0u, misc + 4, &total);
+            if constexpr (GL) ext = max(total, (uint32_t)(off[b1] - lo) + base_off);
             if (total <= (uint32_t)kPreCap) break;
             // rare: growth made PRE overflow; redo with fewer lines
             b1 = b0 + max(1u, nb / 2);
-            __syncthreads();
+            bar();
         }
         // ---- expand markers into PRE (only when some line changed length)
-        st.simple = __syncthreads_or(st.in && !st.bad && marked_lane) == 0;
+        st.simple = bar_or(st.in && !st.bad && marked_lane) == 0;
         if (st.simple) st.P = st.R;
         if (!st.simple && st.in && !st.bad && st.m) {
             uint32_t wpos = st.P;
             const uint32_t end = st.R + st.len;
+            // GL: the next two words already loaded (the stores below keep the
+            // compiler from loading ahead by itself)
+            uint32_t nw1 = 0, nw2 = 0;
+            if constexpr (GL) {
+                nw1 = *(const uint32_t*)(raw + (st.R & ~3u));
+                nw2 = *(const uint32_t*)(raw + (st.R & ~3u) + 4);
+            }
             for (uint32_t w = st.R & ~3u; w < end; w += 4) {
-                const uint32_t word = *(const uint32_t*)(raw + w);
+                uint32_t word;
+                if constexpr (GL) {
+                    word = nw1;
+                    nw1 = nw2;
+                    nw2 = *(const uint32_t*)(raw + w + 8);
+                } else {
+                    word = *(const uint32_t*)(raw + w);
+                }
 #pragma unroll
                 for (int k = 0; k < 4; k++) {
                     const uint32_t x = w + k;
@@ -732,9 +854,10 @@ struct Compressor {
         }
         {
             uint32_t* esc = ESC();
-            for (uint32_t k = tid; k < (uint32_t)kPreCap / 32; k += kWG) esc[k] = 0;
+            const uint32_t words = GL ? min((ext + 32u) / 32u, (uint32_t)kPreCap / 32u) : (uint32_t)kPreCap / 32u;
+            for (uint32_t k = tid; k < words; k += kWG) esc[k] = 0;
         }
-        __syncthreads();
+        bar();
         // ---- parse (backward): automaton + (min,+) window over the next LK costs
         uint32_t cost = 0;
         bool esc_any = false;
@@ -758,9 +881,18 @@ struct Compressor {
             ps.coln = COL[ps.cn];
             uint8_t* sink = smem + L.sink + threadIdx.x;
             const uint32_t Cs = __builtin_amdgcn_readfirstlane(C);
+            // GL: the group's bytes two places back come from a window loaded one group
+            // ahead (a lane whose line has ended reads any in-bounds bytes)
+            Win nwin;
+            if constexpr (GL) nwin = load_win(buf, max((int32_t)top - LK - 1, (int32_t)st.P - LK - 2));
             for (uint32_t base = 0; base < mx; base += LK) {
                 uint32_t escm = 0;
-                parse_steps<0>(ps, buf, base, m, top, (int32_t)st.P, sink, Cs, &escm);
+                Win win;
+                if constexpr (GL) {
+                    win = nwin;
+                    nwin = load_win(buf, max((int32_t)top - (int32_t)(base + LK) - LK - 1, (int32_t)st.P - LK - 2));
+                }
+                parse_steps<0>(ps, buf, base, m, top, (int32_t)st.P, sink, Cs, &escm, win);
                 esc_any |= escm != 0;
                 for (; escm; escm &= escm - 1) {  // rare: bytes with no code of their own
                     const uint32_t pos = top - (base + (uint32_t)__builtin_ctz(escm));
@@ -782,7 +914,7 @@ struct Compressor {
             note_error(A.ws, line_id(k0, b0 + st.j), kErrInval);
         }
         if (st.in) COST()[b0 + st.j] = st.bad ? 0u : cost;
-        st.esc = __syncthreads_or(esc_any) != 0;
+        st.esc = bar_or(esc_any) != 0;
         return b1;
     }
 
@@ -830,8 +962,12 @@ struct Compressor {
                     p = 0;
                     acc = 0;
                 };
+                TokWin tw;
+                if constexpr (GL) tw.init(pre + st.P);
                 while (ic < m) {
-                    const uint32_t t = pre[st.P + ic];
+                    uint32_t t;
+                    if constexpr (GL) t = tw.get(pre + st.P + ic);
+                    else t = pre[st.P + ic];
                     acc |= t << (8 * p);
                     ic += LENT[t];
                     if (++p == 4) put();
@@ -842,10 +978,24 @@ struct Compressor {
             } else if (st.in) {
                 StageWriter wr;
                 wr.begin(stage, (uint32_t)(sbase + oc));
+                TokWin tw;
+                uint32_t ew = 0, ewi = ~0u;  // GL: the escape-bit word last read
+                if constexpr (GL) tw.init(pre + st.P);
                 while (ic < m) {
                     const uint32_t pos = st.P + ic;
-                    const uint32_t t = pre[pos];
-                    if ((esc[pos >> 5] >> (pos & 31)) & 1u) {
+                    uint32_t t, eb;
+                    if constexpr (GL) {
+                        t = tw.get(pre + pos);
+                        if ((pos >> 5) != ewi) {
+                            ewi = pos >> 5;
+                            ew = esc[ewi];
+                        }
+                        eb = ew;
+                    } else {
+                        t = pre[pos];
+                        eb = esc[pos >> 5];
+                    }
+                    if ((eb >> (pos & 31)) & 1u) {
                         wr.add(0x20u | (t << 8), 2);
                         ic += 1;
                     } else {
@@ -856,9 +1006,9 @@ struct Compressor {
                 wr.add('\n', 1);
                 wr.finish();
             }
-            __syncthreads();
+            bar();
             if (!rel) flush_stage(A.out, gb0, gb1, a0, stage);
-            __syncthreads();
+            bar();
             return;
         }
         uint64_t wlo = gb0;
@@ -897,9 +1047,9 @@ struct Compressor {
                 if (ic < m) ic += adv;
                 else nl_done = true;
             }
-            __syncthreads();
+            bar();
             if (!rel) flush_stage(A.out, wlo, whi, a0, stage);
-            __syncthreads();
+            bar();
             wlo = whi;
         }
     }
@@ -924,9 +1074,9 @@ struct Compressor {
             if (A.ids) {
                 // binned mode: this launch's tiles are [first_tile[bin_lo], first_tile[bin_hi])
                 if (tid == 0) misc[2] = atomicAdd(A.ticket, 1u);
-                __syncthreads();
+                bar();
                 t = A.plan->first_tile[A.bin_lo] + misc[2];
-                __syncthreads();
+                bar();
                 have = t < A.plan->first_tile[A.bin_hi];
                 if (have) {
                     uint32_t b = A.bin_lo;
@@ -973,8 +1123,8 @@ struct Compressor {
                     for (uint32_t j = tid; j <= nl; j += kWG) off[j] = A.in_off[k0 + j];
                 }
                 if (tid < kCL) COST()[tid] = 0;
-                __syncthreads();
-                regular = A.ids != nullptr || __syncthreads_and(tid >= nl || frame_error(k0, tid) == 0) != 0;
+                bar();
+                regular = A.ids != nullptr || bar_and(tid >= nl || frame_error(k0, tid) == 0) != 0;
                 // sweep 1: parse every batch, sizes into COST
                 uint32_t b0 = 0;
                 while (b0 < nl) {
@@ -993,7 +1143,7 @@ struct Compressor {
                     const uint64_t ex = lookback_walk(A.status, pt, ptotal);
                     if (tid == 0) ((uint64_t*)misc)[6] = ex;
                 }
-                __syncthreads();
+                bar();
                 const uint64_t pbase = ((uint64_t*)misc)[6];
                 if (tid < pnl) A.out_off[pk0 + tid + 1] = pbase + prel;
                 if (A.out) {
@@ -1003,14 +1153,14 @@ struct Compressor {
                         // into the free LDS buffer; the shifted copy then reads LDS
                         for (uint32_t c = tid; c < (ptotal + 15) / 16; c += kWG)
                             ((uint4*)stage)[c] = ((const uint4*)slot)[c];
-                        __syncthreads();
+                        bar();
                         copy_slot_direct(A.out, stage, ptotal, pbase);
                     } else if (tid == 0) {
                         atomicOr(&A.ws->enospc, 1u);
                     }
                 }
                 pend = false;
-                __syncthreads();
+                bar();
             }
             if (!have) break;
             if (t == 0 && tid == 0) A.out_off[0] = 0;
@@ -1034,7 +1184,7 @@ struct Compressor {
                     const uint64_t ex = lookback_walk(A.status, t, total);
                     if (tid == 0) ((uint64_t*)misc)[6] = ex;
                 }
-                __syncthreads();
+                bar();
                 const uint64_t gbase = ((uint64_t*)misc)[6];
                 if (tid < nl) A.out_off[k0 + tid + 1] = gbase + e + mylen;
                 const bool fits = gbase + total <= A.out_cap;
@@ -1052,25 +1202,37 @@ struct Compressor {
                     }
                 }
             }
-            __syncthreads();
+            bar();
         }
         finish_workgroup(A.ws, A.res, gridDim.x);
     }
 };
 
-template <int LK, int CAP, int MODE = kModeCompress>
-__global__ void __launch_bounds__(kWG) compress_kernel(CompressArgs a) {
+template <int LK, int CAP, int MODE, bool GL>
+__device__ __forceinline__ void compress_body(const CompressArgs& a) {
     extern __shared__ __align__(16) uint8_t smem[];
     // stage the dictionary image (up to EXP) in LDS
     {
         const uint4* src = (const uint4*)a.tables;
         uint4* dst = (uint4*)smem;
         for (uint32_t k = threadIdx.x; k < a.tab_bytes / 16; k += kWG) dst[k] = src[k];
-        smem[compress_lds(a.tab_bytes, CAP).ident + threadIdx.x] = (uint8_t)threadIdx.x;
+        smem[compress_lds(a.tab_bytes, CAP, GL).ident + threadIdx.x] = (uint8_t)threadIdx.x;
     }
     __syncthreads();
-    Compressor<LK, CAP, MODE> c(a, smem);
+    Compressor<LK, CAP, MODE, GL> c(a, smem);
     c.run();
+}
+
+template <int LK, int CAP, int MODE = kModeCompress>
+__global__ void __launch_bounds__(kWG) compress_kernel(CompressArgs a) {
+    compress_body<LK, CAP, MODE, false>(a);
+}
+
+// The global-memory layout holds little in LDS, so its occupancy is set by
+// registers: kept at three waves per SIMD (at most 168 VGPRs).
+template <int LK>
+__global__ void __launch_bounds__(kWG, 3) compress_kernel_gl(CompressArgs a) {
+    compress_body<LK, kCapGlobal, kModeCompress, true>(a);
 }
 
 // ============================================================================
@@ -2487,6 +2649,7 @@ struct BinnedWs {
     uint32_t* ptotal;  // placement tile totals
     uint64_t* pbase;   // their exclusive prefix, + 1
     uint8_t* staging;
+    uint8_t* glines;   // line buffers of the global-memory layout, kGlStride per workgroup
     size_t bytes;
     uint32_t max_tiles, nchunks, ptiles;
 };
@@ -2518,6 +2681,7 @@ BinnedWs binned_ws(void* ws, uint64_t n, uint64_t out_cap, int cus) {
     w.ptotal = (uint32_t*)take((size_t)w.ptiles * 4);
     w.pbase = (uint64_t*)take(((size_t)w.ptiles + 1) * 8);
     w.staging = take(out_cap + 16);
+    w.glines = take(grid * kGlStride);
     w.bytes = o;
     return w;
 }
@@ -2660,15 +2824,18 @@ static zs_status launch_init(WsHeader* h, uint64_t* status, uint32_t ntiles, Res
 // One compression launch: the persistent grid of the LDS variant, at most
 // max_tiles workgroups.  tab_bytes: dictionary image staged (0: none, for
 // pre-processing only); lk: the parse window of the dictionary (8 or 16).
-static zs_status launch_compress(uint32_t tab_bytes, uint32_t lk, const CompressArgs& a, bool large,
+static zs_status launch_compress(uint32_t tab_bytes, uint32_t lk, const CompressArgs& a, uint32_t layout,
                                  uint32_t max_tiles, int cus, hipStream_t s, int mode = kModeCompress) {
-    // plain: kCapSmall; binned: kCapGather, or kCapLarge for the bins that ask for it
-    const int cap = large ? kCapLarge : (a.ids ? kCapGather : kCapSmall);
-    const CompressLds cl = compress_lds(tab_bytes, cap);
+    // plain: kCapSmall; binned: kCapGather, or for the bins that ask for it kCapLarge
+    // (layout 1) or the global-memory line buffers (layout 2)
+    const bool gl = layout == 2;
+    const int cap = gl ? kCapGlobal : layout == 1 ? kCapLarge : (a.ids ? kCapGather : kCapSmall);
+    const CompressLds cl = compress_lds(tab_bytes, cap, gl);
     const uint32_t lds = a.ids ? cl.total_gather : cl.total;
     const bool k8 = lk == 8;
     const void* kfn = mode == kModePre    ? (const void*)compress_kernel<8, kCapSmall, kModePre>
                       : mode == kModePost ? (const void*)compress_kernel<8, kCapSmall, kModePost>
+                      : gl ? (k8 ? (const void*)compress_kernel_gl<8> : (const void*)compress_kernel_gl<16>)
                       : cap == kCapLarge  ? (k8 ? (const void*)compress_kernel<8, kCapLarge>
                                                 : (const void*)compress_kernel<16, kCapLarge>)
                       : cap == kCapGather ? (k8 ? (const void*)compress_kernel<8, kCapGather>
@@ -2724,7 +2891,8 @@ static zs_status compress_plain(const zs_dict* d, const uint8_t* in, uint64_t in
     a.plan = nullptr;
     a.bin_lo = a.bin_hi = 0;
     a.ticket = nullptr;
-    return launch_compress(a.tab_bytes, d ? d->lk : 8u, a, false, ntiles, di.cus, s, mode);
+    a.glines = nullptr;
+    return launch_compress(a.tab_bytes, d ? d->lk : 8u, a, 0, ntiles, di.cus, s, mode);
 }
 
 zs_status zs_compress(const zs_dict* d, const uint8_t* in, uint64_t in_bytes, const uint64_t* in_off,
@@ -2772,7 +2940,7 @@ zs_status zs_compress_binned(const zs_dict* d, const uint8_t* in, uint64_t in_by
     for (uint32_t i = 0; i + 1 < nb; i++)
         if (cfg->edges[i] == 0 || (i > 0 && cfg->edges[i] <= cfg->edges[i - 1])) return ZS_EINVAL;
     for (uint32_t i = 0; i < nb; i++)
-        if (cfg->lines_per_tile[i] < kMinLpt || cfg->lines_per_tile[i] > (uint32_t)kCL || cfg->large_lds[i] > 1)
+        if (cfg->lines_per_tile[i] < kMinLpt || cfg->lines_per_tile[i] > (uint32_t)kCL || cfg->large_lds[i] > 2)
             return ZS_EINVAL;
     DeviceInfo di = device_info();
     if (!di.ok) return ZS_EDEVICE;
@@ -2833,6 +3001,7 @@ zs_status zs_compress_binned(const zs_dict* d, const uint8_t* in, uint64_t in_by
     a.res = nullptr;
     a.ids = w.ids;
     a.plan = w.plan;
+    a.glines = w.glines;
     uint32_t b = 0, launch = 0;
     while (b < nb) {
         uint32_t e = b + 1;
@@ -2843,7 +3012,7 @@ zs_status zs_compress_binned(const zs_dict* d, const uint8_t* in, uint64_t in_by
         // an upper bound of this launch's tiles sizes the grid
         uint64_t most = 0;
         for (uint32_t k = b; k < e; k++) most += (n_lines + bi.lpt[k] - 1) / bi.lpt[k];
-        if (launch_compress(d->comp_bytes, d->lk, a, large[b] != 0, (uint32_t)std::min<uint64_t>(most, w.max_tiles),
+        if (launch_compress(d->comp_bytes, d->lk, a, large[b], (uint32_t)std::min<uint64_t>(most, w.max_tiles),
                             di.cus, s) != ZS_OK)
             return ZS_EDEVICE;
         b = e;
@@ -2953,7 +3122,7 @@ zs_status zs_autotune_binned(const zs_dict* d, const uint8_t* in, uint64_t in_by
         if (e.size() != es.size() && !es.empty()) continue;  // a degenerate set repeats a smaller one
         const uint32_t nb = (uint32_t)e.size() + 1;
         for (uint32_t lpt : {256u, 128u, 64u, 32u}) {
-            for (uint32_t lg : {0u, 1u}) {
+            for (uint32_t lg : {0u, 1u, 2u}) {
                 if (nb == 1 && lpt != 256) continue;
                 zs_bin_config c;
                 memset(&c, 0, sizeof c);

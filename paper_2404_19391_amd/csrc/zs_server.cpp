@@ -118,6 +118,7 @@ struct Request {
     zs_result* d_res = nullptr;
     uint8_t* d_out = nullptr;
     uint64_t total = 0;
+    uint64_t opt_cap = 0;  // compression: output bytes reserved before the size is known
     // host outputs (pinned)
     uint8_t* h_out = nullptr;   // result word, offsets, bytes
     double t_submit = 0, t_admit = 0, t_done = 0;
@@ -170,11 +171,18 @@ namespace {
 
 uint64_t a256(uint64_t x) { return (x + 255) & ~(uint64_t)255; }
 
+// Output bytes a compression request reserves before its size is known: its
+// input size plus a newline per line holds any line that does not grow
+// (every SMILES-alphabet line with the default dictionary); a larger output
+// ends the first call with ZS_ENOSPC and complete offsets, and the request is
+// run again with an output of the exact size.
+uint64_t optimistic_cap(const Request* r) { return r->in_bytes + r->n; }
+
 // Device bytes a request needs before its output size is known.
 uint64_t stage1_bytes(const Request* r) {
     uint64_t b = a256((r->n + 1) * 8) + a256(sizeof(zs_result)) + a256(r->ws_bytes);
     if (r->kind == kDecompress) b += a256(r->n * 8);
-    else b += a256(r->in_bytes + 16) + a256((r->n + 1) * 8);
+    else b += a256(r->in_bytes + 16) + a256((r->n + 1) * 8) + a256(optimistic_cap(r) + 16);
     return b;
 }
 
@@ -198,8 +206,12 @@ bool start_sizing(zs_server* s, Slot& sl, Request* r) {
     r->d_res = (zs_result*)s->dev.alloc(sizeof(zs_result));
     r->d_ws = s->dev.alloc(r->ws_bytes);
     r->d_in = s->dev.alloc(r->kind == kDecompress ? r->n * 8 : a256(r->in_bytes + 16) + (r->n + 1) * 8);
+    if (r->kind == kCompress) {
+        r->opt_cap = optimistic_cap(r);
+        r->d_out = s->dev.alloc(r->opt_cap + 16);
+    }
     uint8_t* hres = s->host.alloc(64);
-    if (!r->d_off || !r->d_res || !r->d_ws || !r->d_in || !hres) {
+    if (!r->d_off || !r->d_res || !r->d_ws || !r->d_in || !hres || (r->kind == kCompress && !r->d_out)) {
         free_device(s, r);
         s->host.release(hres);
         return false;
@@ -213,11 +225,14 @@ bool start_sizing(zs_server* s, Slot& sl, Request* r) {
         note(r, zs_decompress_lines(s->dict, sh.in, sh.in_bytes, sh.off, sh.n, (const uint64_t*)r->d_in, r->n,
                                     nullptr, 0, r->d_off, r->d_ws, r->ws_bytes, r->d_res, st));
     } else {
+        // compression runs at once into the reserved output; the offsets are
+        // complete even when the output does not fit
         const uint64_t* doff = (const uint64_t*)(r->d_in + a256(r->in_bytes + 16));
-        note(r, zs_compress(s->dict, r->d_in, r->in_bytes, doff, r->n, nullptr, 0, r->d_off, r->flags, r->d_ws,
-                            r->ws_bytes, r->d_res, st));
+        note(r, zs_compress(s->dict, r->d_in, r->in_bytes, doff, r->n, r->d_out, r->opt_cap, r->d_off, r->flags,
+                            r->d_ws, r->ws_bytes, r->d_res, st));
     }
     if (!r->fail) note_hip(r, hipMemcpyAsync(r->h_out, r->d_off + r->n, 8, hipMemcpyDeviceToHost, st));
+    if (!r->fail) note_hip(r, hipMemcpyAsync(r->h_out + 16, r->d_res, sizeof(zs_result), hipMemcpyDeviceToHost, st));
     note_hip(r, hipEventRecord(sl.ev, st));
     r->stage = kSizing;
     r->slot = (int)(&sl - s->slots.data());
@@ -226,11 +241,37 @@ bool start_sizing(zs_server* s, Slot& sl, Request* r) {
     return true;
 }
 
-// Stage 2: the output buffer of the exact size, the call, the copies back.
+// Stage 2: the output buffer of the exact size, the call, the copies back; a
+// compression whose output fitted the reserved buffer only copies back.
 // Returns false (and waits) if the arenas cannot hold the output yet.
 bool start_running(zs_server* s, Slot& sl, Request* r) {
     memcpy(&r->total, r->h_out, 8);
     if (r->fail) r->total = 0;
+    if (r->kind == kCompress && !r->fail) {
+        zs_result first;
+        memcpy(&first, r->h_out + 16, sizeof first);
+        if (first.code != ZS_ENOSPC && r->total <= r->opt_cap) {
+            const uint64_t hb = 64 + a256((r->n + 1) * 8) + r->total + 16;
+            uint8_t* hout = s->host.alloc(hb);
+            if (!hout) return false;
+            s->host.release(r->h_out);
+            r->h_out = hout;
+            r->footprint = stage1_bytes(r);
+            hipStream_t st = sl.stream;
+            memset(r->h_out, 0, 64);
+            note_hip(r, hipMemcpyAsync(r->h_out, r->d_res, sizeof(zs_result), hipMemcpyDeviceToHost, st));
+            note_hip(r, hipMemcpyAsync(r->h_out + 64, r->d_off, (r->n + 1) * 8, hipMemcpyDeviceToHost, st));
+            if (r->total)
+                note_hip(r, hipMemcpyAsync(r->h_out + 64 + a256((r->n + 1) * 8), r->d_out, r->total,
+                                           hipMemcpyDeviceToHost, st));
+            note_hip(r, hipEventRecord(sl.ev, st));
+            r->stage = kRunning;
+            return true;
+        }
+        // larger than reserved: give the reservation back and run again at the exact size
+        s->dev.release(r->d_out);
+        r->d_out = nullptr;
+    }
     uint8_t* dout = s->dev.alloc(r->total + 16);
     const uint64_t hb = 64 + a256((r->n + 1) * 8) + r->total + 16;
     uint8_t* hout = s->host.alloc(hb);

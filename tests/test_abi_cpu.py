@@ -218,7 +218,7 @@ def test_binned_config_validation():
     bad = [zs.BinConfig.make(edges=(128, 128)), zs.BinConfig.make(edges=(256, 128)),
            zs.BinConfig.make(edges=(0,)), zs.BinConfig.make(lines_per_tile=(0,)),
            zs.BinConfig.make(lines_per_tile=(31,)), zs.BinConfig.make(edges=(64,), lines_per_tile=(256, 7)),
-           zs.BinConfig.make(lines_per_tile=(257,)), zs.BinConfig.make(large_lds=(2,))]
+           zs.BinConfig.make(lines_per_tile=(257,)), zs.BinConfig.make(large_lds=(3,))]
     for c in bad:
         assert call(c) == zs.EINVAL
     c = zs.BinConfig.make()

@@ -18,6 +18,9 @@ CONFIGS = [
     dict(edges=(64, 256), lines_per_tile=(256, 128, 32), large_lds=(0, 0, 1)),
     dict(edges=(16, 32, 48, 64, 96, 128, 400), lines_per_tile=(256, 200, 160, 128, 96, 64, 33, 32),
          large_lds=(1, 0, 1, 0, 1, 0, 1, 0)),
+    # line buffers in global memory: for the long bin, and for every bin
+    dict(edges=(128,), lines_per_tile=(256, 256), large_lds=(0, 2)),
+    dict(edges=(64, 256), lines_per_tile=(256, 128, 64), large_lds=(2, 2, 2)),
 ]
 
 

@@ -158,3 +158,19 @@ def test_output_that_can_never_fit_ends_with_enospc(zs, gd, odict):
     st = srv.stats()
     assert st["device_bytes_in_use"] == 0
     srv.close()
+
+
+def test_compress_output_larger_than_input(zs, gd, shard, odict):
+    """A compression request whose output is larger than its input (bytes with no code
+    are escaped, two bytes each): the first call, into an output the size of the input,
+    ends with ZS_ENOSPC and the request runs again at the exact size; the reply is the
+    oracle's.  Beside it, a request whose output fits the first call."""
+    srv, sid = _server(zs, gd, shard, slots=2, device_bytes=64 << 20, host_bytes=64 << 20)
+    big = [b"a" * 50, b"CC(=O)aa", b"", b"x" * 4000] * 50
+    small = smilesgen.lines("bulk", 106, 500)
+    for lines in (big, small):
+        buf, off = oracle.join_lines(lines)
+        want = oracle.compress(odict, buf, off)
+        got = srv.wait(srv.submit_compress(buf, off))
+        assert _same(got, want)
+    srv.close()
