@@ -162,7 +162,7 @@ int zsi_compile_dict(const uint8_t* len, const uint8_t* exp, std::vector<uint8_t
     h.off_col = o;   o = align16(o + 256);
     h.off_code1 = o; o = align16(o + 256);
     h.off_trans = o; o = align16(o + (uint32_t)(S * ncols * 2));
-    h.off_outk = o;  o = align16(o + (uint32_t)(S * lk * 4));
+    h.off_outk = o;  o = align16(o + (uint32_t)(S * lk));
     h.off_code = o;  o = align16(o + (uint32_t)(S * lk));
     h.off_exp = o;   o = align16(o + 256 * kExpStride);
     h.blob_bytes = o;
@@ -176,13 +176,13 @@ int zsi_compile_dict(const uint8_t* len, const uint8_t* exp, std::vector<uint8_t
         memcpy(&blob[h.off_exp + b * kExpStride], exp + b * kExpStride, (size_t)len[b]);
     }
     uint16_t* trans = (uint16_t*)&blob[h.off_trans];
-    uint32_t* outk = (uint32_t*)&blob[h.off_outk];
+    int8_t* outk = (int8_t*)&blob[h.off_outk];
     uint8_t* code = &blob[h.off_code];
     for (int s = 0; s < S; s++) {
         for (int c = 0; c < ncols; c++) trans[s * ncols + c] = (uint16_t)delta[s][c];
         for (int L = 1; L <= lk; L++) {
             int cd = out_code[s][L];
-            outk[s * lk + (L - 1)] = cd >= 0 ? (uint32_t)(31 - L) : 0xFFFFFFFFu;
+            outk[s * lk + (L - 1)] = cd >= 0 ? (int8_t)(31 - L) : (int8_t)-1;
             code[s * lk + (L - 1)] = cd > 0 ? (uint8_t)cd : 0;
         }
     }

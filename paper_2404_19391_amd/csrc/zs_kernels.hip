@@ -60,7 +60,7 @@ constexpr int kCapGlobal = 262144;
 constexpr size_t kGlStride = 2 * (size_t)kCapGlobal + kCapGlobal / 8 + 256;  // RAW, PRE, ESC bits, margins
 constexpr int kSlots = 8;             // fast ring table (registers): up to 8 open rings, found by label
 constexpr int kSlotsFirst = 4;        // the smaller table tried first
-constexpr int kSlotsLong = 16;        // the table of the global-memory layout (long lines)
+constexpr int kSlotsLong = 32;        // the table of the global-memory layout (long lines: 16-25 rings open at once)
 constexpr int kGenLane = 400;         // per-lane ring tables in global memory (any line):
                                       // 100 open positions u16 + 100 last-close u16
 static_assert(kCapGather >= 3 * (int)ZS_MAX_LINE, "a pre-processed line must fit");
@@ -238,7 +238,7 @@ struct Compressor {
     const uint8_t* LENT;  // expansion lengths
     const uint8_t* COL;
     const uint16_t* TRANS;
-    const uint32_t* OUTK;
+    const uint8_t* OUTK;  // signed bytes, LK per state
     uint32_t off_code1, off_code;
     uint32_t C;  // automaton columns
 
@@ -255,7 +255,7 @@ struct Compressor {
             LENT = smem + H->off_len;
             COL = smem + H->off_col;
             TRANS = (const uint16_t*)(smem + H->off_trans);
-            OUTK = (const uint32_t*)(smem + H->off_outk);
+            OUTK = smem + H->off_outk;
             off_code1 = H->off_code1;
             off_code = H->off_code;
             C = H->ncols;
@@ -571,13 +571,26 @@ struct Compressor {
                     cnn = buf[max(pos, P) - 2];  // may read just before the line: any byte will do
                 }
                 const uint32_t colnn = COL[cnn];
-                const uint32_t* ok = OUTK + s * LK;
+                // the state's key bits for L = 1..LK, one signed byte each (-1: no pattern),
+                // in one 8- or 16-byte LDS read; sign-extended, each ORs into a cost key
+                uint32_t kw[LK / 4];
+                if constexpr (LK == 8) {
+                    const uint2 v = *(const uint2*)(OUTK + s * LK);
+                    kw[0] = v.x;
+                    kw[1] = v.y;
+                } else {
+                    const uint4 v = *(const uint4*)(OUTK + s * LK);
+                    kw[0] = v.x;
+                    kw[1] = v.y;
+                    kw[2] = v.z;
+                    kw[3] = v.w;
+                }
                 uint32_t Kmin = ps.V[(K + LK - 1) % LK] + 63u;  // escape: cost[i+1] + 2, low bits 31
 #pragma unroll
-                for (int q = 0; q < LK; q += 4) {
-                    const uint4 kv = *(const uint4*)(ok + q);
-                    Kmin = min(Kmin, min(ps.V[(K + 2 * LK - 1 - q) % LK] | kv.x, ps.V[(K + 2 * LK - 2 - q) % LK] | kv.y));
-                    Kmin = min(Kmin, min(ps.V[(K + 2 * LK - 3 - q) % LK] | kv.z, ps.V[(K + 2 * LK - 4 - q) % LK] | kv.w));
+                for (int q = 0; q < LK; q += 2) {
+                    const uint32_t e0 = (uint32_t)(int32_t)(int8_t)(kw[q >> 2] >> (8 * (q & 3)));
+                    const uint32_t e1 = (uint32_t)(int32_t)(int8_t)(kw[(q + 1) >> 2] >> (8 * ((q + 1) & 3)));
+                    Kmin = min(Kmin, min(ps.V[(K + 2 * LK - 1 - q) % LK] | e0, ps.V[(K + 2 * LK - 2 - q) % LK] | e1));
                 }
                 const uint32_t ch = 31u - (Kmin & 31u);
                 // the byte to store, always one load: the code of length ch, the
@@ -770,7 +783,7 @@ struct Compressor {
             if (run_rings) {
                 bool ok;
                 if constexpr (GL) {
-                    // long lines hold more rings open at once: one table of 16 slots
+                    // long lines hold more rings open at once: one table of 32 slots
                     ok = ring_fast<kSlotsLong, post>(raw, st.R, list, nlab, maxlab, &delta, &overflow, &marked);
                 } else {
                     // a table of 4 slots first (more rings than that are rarely open at

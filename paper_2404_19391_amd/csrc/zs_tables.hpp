@@ -9,9 +9,10 @@
 //   COL  [256]      u8   byte -> column of the match automaton
 //   CODE1[256]      u8   byte -> code whose expansion is that single byte (0 = none)
 //   TRANS[S][C]     u16  automaton transition, state x column -> state
-//   OUTK [S][LK]    u32  per state and length L = 1..LK: the low bits of the DP
+//   OUTK [S][LK]    i8   per state and length L = 1..LK: the low bits of the DP
 //                        key when a pattern of length L starts here (31 - L),
-//                        or 0xFFFFFFFF when none does
+//                        or -1 when none does (sign-extended, it disables the
+//                        length in the key's OR: 0xFFFFFFFF)
 //   CODE [S][LK]    u8   per state and length L >= 2: the code of that pattern
 //   EXP  [256][16]  u8   expansion bytes (decoder table, Sec. IV-D-2)
 //

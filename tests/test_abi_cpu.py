@@ -79,7 +79,9 @@ class Tables:
         self.col = b[o_col:o_col + 256]
         self.code1 = b[o_code1:o_code1 + 256]
         self.trans = np.frombuffer(blob, dtype=np.uint16, count=self.S * self.C, offset=o_trans).reshape(self.S, self.C)
-        self.outk = np.frombuffer(blob, dtype=np.uint32, count=self.S * self.lk, offset=o_outk).reshape(self.S, self.lk)
+        # signed bytes: 31 - L, or -1 (as a 32-bit key mask: 0xFFFFFFFF) where no pattern of length L starts
+        self.outk = (np.frombuffer(blob, dtype=np.int8, count=self.S * self.lk, offset=o_outk).astype(np.int64)
+                     & 0xFFFFFFFF).astype(np.uint32).reshape(self.S, self.lk)
         self.code = b[o_code:o_code + self.S * self.lk].reshape(self.S, self.lk)
         self.exp = b[o_exp:o_exp + 256 * 16].reshape(256, 16)
 
