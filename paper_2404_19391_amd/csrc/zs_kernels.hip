@@ -51,7 +51,9 @@ constexpr int kCL = 256;              // lines per tile at most (one per thread)
 // their pre-processed form: the default variant runs 3 workgroups per CU, the
 // large one (long lines) 2.
 constexpr int kCapSmall = 14336;
-constexpr int kCapGather = 13312;  // binned short bins: room for the ABS array at 3 workgroups per CU
+// binned short bins: a tile of 256 bulk lines (13.2 KB on average) fits one batch,
+// and with the default dictionary three workgroups (ABS array included) fit a CU
+constexpr int kCapGather = 15360;
 constexpr int kCapLarge = 26624;
 // Global-memory layout (long-line bins): the line buffers of a workgroup live in
 // its own region of the workspace, so LDS holds only the automaton and the
