@@ -59,10 +59,12 @@ constexpr int kCapLarge = 26624;
 // its own region of the workspace, so LDS holds only the automaton and the
 // per-line arrays and a tile of 256 long lines keeps every lane busy.
 constexpr int kCapGlobal = 262144;
-constexpr size_t kGlStride = 2 * (size_t)kCapGlobal + kCapGlobal / 8 + 256;  // RAW, PRE, ESC bits, margins
+constexpr int kLabels = 100;  // ring label values 0..99
+// RAW, PRE, ESC bits, the label tables of the ring IDs (u16 per label and lane), margins
+constexpr size_t kGlStride = 2 * (size_t)kCapGlobal + kCapGlobal / 8 + 256 + (size_t)kLabels * kWG * 2;
+constexpr size_t kGlTab = 2 * (size_t)kCapGlobal + kCapGlobal / 8 + 256;  // offset of the label tables
 constexpr int kSlots = 8;             // fast ring table (registers): up to 8 open rings, found by label
 constexpr int kSlotsFirst = 4;        // the smaller table tried first
-constexpr int kSlotsLong = 32;        // the table of the global-memory layout (long lines: 16-25 rings open at once)
 constexpr int kGenLane = 400;         // per-lane ring tables in global memory (any line):
                                       // 100 open positions u16 + 100 last-close u16
 static_assert(kCapGather >= 3 * (int)ZS_MAX_LINE, "a pre-processed line must fit");
@@ -236,6 +238,7 @@ struct Compressor {
     uint8_t* g_raw = nullptr;  // GL: this workgroup's line buffers in global memory
     uint8_t* g_pre = nullptr;
     uint32_t* g_esc = nullptr;
+    uint16_t* g_tab = nullptr;  // GL: label tables of the ring IDs, one column per lane
     const TableHeader* H;
     const uint8_t* LENT;  // expansion lengths
     const uint8_t* COL;
@@ -251,6 +254,7 @@ struct Compressor {
             g_raw = b;
             g_pre = b + CAP;
             g_esc = (uint32_t*)(b + 2 * (size_t)CAP);
+            g_tab = (uint16_t*)(a.glines + (uint64_t)blockIdx.x * kGlStride + kGlTab);
         }
         H = (const TableHeader*)smem;
         if constexpr (MODE == kModeCompress) {
@@ -324,13 +328,15 @@ struct Compressor {
     // Forward scan of one raw line, four bytes at a time with byte-parallel
     // masks (one flag bit per byte, at bit 7 of each byte): bad bytes, bracket
     // depth, ring labels - a digit outside brackets, or '%' outside brackets
-    // followed by two digits (Sec. II).  Labels go to `list` (u16: position in
-    // the line << 4, low bits the digit, or 15 for a '%' label).
+    // followed by two digits (Sec. II).  Labels go to `list`: u16 entries hold
+    // the position in the line << 4 and the digit, or 15 for a '%' label; u32
+    // entries the position << 8, 0x80 for a '%' label and the label value.
     __device__ static inline uint32_t eq_bytes(uint32_t w, uint32_t pat) {
         const uint32_t x = w ^ pat;
         return ~(((x & 0x7F7F7F7Fu) + 0x7F7F7F7Fu) | x) & 0x80808080u;
     }
-    __device__ __forceinline__ void scan_labels(const uint8_t* raw, uint32_t R, uint32_t len, uint16_t* list, uint32_t cap,
+    template <typename E>
+    __device__ __forceinline__ void scan_labels(const uint8_t* raw, uint32_t R, uint32_t len, E* list, uint32_t cap,
                                 uint32_t* nlab_out, bool* corrupt_out, bool* malformed_out, bool* over_out,
                                 bool* has_pct) {
         uint32_t inbr = 0;      // bracket state before the current word (0 or 0x80808080-style all-ones flag)
@@ -339,16 +345,12 @@ struct Compressor {
         uint32_t bad = 0, mal = 0, pct_any = 0;
         bool over = false;
         const uint32_t end = R + len;
-        const uint32_t w0 = R & ~3u;
-        // two words in flight ahead of the one being classified
-        uint32_t word = *(const uint32_t*)(raw + w0);
-        uint32_t next = *(const uint32_t*)(raw + w0 + 4);
-        for (uint32_t w = w0; w < end; w += 4) {
-            const uint32_t next2 = *(const uint32_t*)(raw + w + 8);
+        // one word: w its position (w < end), next the word after it
+        auto step = [&](uint32_t w, uint32_t word, uint32_t next) __attribute__((always_inline)) {
             // flag bits of the bytes of this word that belong to the line
             // (clamps in signed arithmetic: see the note at the decoder's valid mask)
-            const uint32_t lo = (uint32_t)max((int32_t)R - (int32_t)w, 0), hi = min(end - w, 4u);
-            const uint32_t inl = (0x80808080u << (8 * lo)) & (0x80808080u >> (8 * (4 - hi)));
+            const uint32_t lo = (uint32_t)min(max((int32_t)R - (int32_t)w, 0), 4), hi = min(end - w, 4u);
+            const uint32_t inl = lo >= 4 ? 0u : (0x80808080u << (8 * lo)) & (0x80808080u >> (8 * (4 - hi)));
             const uint32_t nhi = (uint32_t)min(max((int32_t)end - (int32_t)w - 4, 0), 4);
             const uint32_t inl_n = nhi ? (0x80808080u >> (8 * (4 - nhi))) : 0u;
             // byte classes (valid only for bytes < 0x80; other bytes are corrupt anyway)
@@ -383,17 +385,50 @@ struct Compressor {
 #pragma unroll
                 for (int k = 0; k < 4; k++) {
                     if (lab & (0x80u << (8 * k))) {
-                        // entry: line position << 4 | digit value, or 15 for '%'
                         const uint32_t cb = (word >> (8 * k)) & 0xFFu;
-                        const uint32_t dv = (cb == '%') ? 15u : cb - '0';
-                        if (nlab < cap) list[nlab] = (uint16_t)(((w + k - R) << 4) | dv);
+                        uint32_t ent;
+                        if constexpr (sizeof(E) == 2) {
+                            ent = ((w + k - R) << 4) | ((cb == '%') ? 15u : cb - '0');
+                        } else {
+                            // a '%' label's two digits are in this word or the next
+                            const uint64_t wn = (uint64_t)word | ((uint64_t)next << 32);
+                            const uint32_t d1 = (uint32_t)(wn >> (8 * (k + 1))) & 0xFFu;
+                            const uint32_t d2 = (uint32_t)(wn >> (8 * (k + 2))) & 0xFFu;
+                            ent = ((w + k - R) << 8) |
+                                  ((cb == '%') ? (0x80u | (((d1 - '0') * 10u + (d2 - '0')) & 0x7Fu)) : cb - '0');
+                        }
+                        if (nlab < cap) list[nlab] = (E)ent;
                         else over = true;
                         nlab++;
                     }
                 }
             }
-            word = next;
-            next = next2;
+        };
+        if constexpr (sizeof(E) == 4) {
+            // global-memory layout: 16-byte loads, one chunk in flight ahead
+            const uint32_t c0 = R & ~15u;
+            uint4 cu = *(const uint4*)(raw + c0);
+            uint4 nx = *(const uint4*)(raw + c0 + 16);
+            for (uint32_t c = c0; c < end; c += 16) {
+                const uint4 n2 = *(const uint4*)(raw + c + 32);  // at most 47 bytes past the line: in the buffer
+                step(c, cu.x, cu.y);
+                if (c + 4 < end) step(c + 4, cu.y, cu.z);
+                if (c + 8 < end) step(c + 8, cu.z, cu.w);
+                if (c + 12 < end) step(c + 12, cu.w, nx.x);
+                cu = nx;
+                nx = n2;
+            }
+        } else {
+            const uint32_t w0 = R & ~3u;
+            // two words in flight ahead of the one being classified
+            uint32_t word = *(const uint32_t*)(raw + w0);
+            uint32_t next = *(const uint32_t*)(raw + w0 + 4);
+            for (uint32_t w = w0; w < end; w += 4) {
+                const uint32_t next2 = *(const uint32_t*)(raw + w + 8);
+                step(w, word, next);
+                word = next;
+                next = next2;
+            }
         }
         *nlab_out = nlab;
         *corrupt_out = bad != 0;
@@ -499,6 +534,80 @@ struct Compressor {
         return opens == 0;
     }
 
+    // Ring IDs of the global-memory layout (long lines, many rings open at once):
+    // the rule of Sec. IV-A as "latest close per ID", like ring_general, from
+    // the u32 label list.  The open ring of label v sits in this lane's column
+    // of the label table (entry v: opening position + 1, 0x8000 for a '%'
+    // label, 0 when closed; all zero between lines), the latest closing
+    // position of IDs 0..31 in registers.  The table entry of the next label is
+    // loaded one step ahead and taken from this step when the label repeats.
+    // Sets *overflow when an ID reaches 32 (the caller restores the line and
+    // takes ring_general); returns false when rings stay open.  Either way the
+    // table is cleared again.
+    __device__ __forceinline__ bool ring_table(uint8_t* raw, uint32_t R, const uint32_t* list, uint32_t nlab,
+                                               uint32_t maxlab, int* delta, bool* overflow, bool* marked) {
+        uint16_t* tab = g_tab + threadIdx.x;  // entry v at tab[v * kWG]
+        uint32_t lct[32];                     // closing position + 1 of the latest ring that took ID k; 0: none
+#pragma unroll
+        for (int k = 0; k < 32; k++) lct[k] = 0;
+        bool mk_any = false, ovf = false;
+        int dl = 0, opens = 0;
+        uint32_t e0 = list[0], e1 = list[1];  // entries past the end: unused bytes of PRE, never processed
+        uint32_t t0 = tab[min(e0 & 0x7Fu, 99u) * kWG];
+        for (uint32_t q = 0; q < maxlab; q++) {
+            const uint32_t ent = e0, cur = t0;
+            const uint32_t v = min(ent & 0x7Fu, 99u);
+            e0 = e1;
+            e1 = list[q + 2];
+            const uint32_t vn = min(e0 & 0x7Fu, 99u);
+            t0 = tab[vn * kWG];
+            uint32_t nv = cur;
+            if (q < nlab && !ovf) {
+                const uint32_t p = ent >> 8;
+                const uint32_t tl = (ent & 0x80u) ? 3u : 1u;
+                if (cur == 0) {
+                    nv = (p + 1) | (tl == 3 ? 0x8000u : 0u);
+                    opens++;
+                } else {
+                    const uint32_t o = (cur & 0x7FFFu) - 1;
+                    // IDs taken by a ring that closed after this one opened
+                    uint32_t M = 0;
+#pragma unroll
+                    for (int k = 31; k >= 0; k--) M = (M << 1) | (lct[k] > o + 1 ? 1u : 0u);
+                    if (M == 0xFFFFFFFFu) {
+                        ovf = true;
+                    } else {
+                        const uint32_t id = (uint32_t)__builtin_ctz(~M);
+#pragma unroll
+                        for (int k = 0; k < 32; k++) lct[k] = ((uint32_t)k == id) ? p + 1 : lct[k];
+                        nv = 0;
+                        opens--;
+                        const uint32_t to = (cur & 0x8000u) ? 3u : 1u;
+                        const int nlen = id < 10 ? 1 : 3;
+                        // a one-byte label that stays one byte takes its new digit in place;
+                        // anything else is marked for the expansion pass
+                        const uint8_t nb = (nlen == 1) ? (uint8_t)('0' + id) : (uint8_t)(kIdMark | id);
+                        raw[R + o] = (to == 1) ? nb : (uint8_t)(kIdMark | id);
+                        if (to == 3) raw[R + o + 1] = raw[R + o + 2] = kSkip;
+                        raw[R + p] = (tl == 1) ? nb : (uint8_t)(kIdMark | id);
+                        if (tl == 3) raw[R + p + 1] = raw[R + p + 2] = kSkip;
+                        mk_any |= (nlen != 1) | (to != 1) | (tl != 1);
+                        dl += (nlen - (int)to) + (nlen - (int)tl);
+                    }
+                }
+                if (nv != cur) tab[v * kWG] = (uint16_t)nv;
+            }
+            if (vn == v) t0 = nv;  // loaded before this step's store
+        }
+        if (ovf || opens != 0) {
+            for (uint32_t q = 0; q < nlab; q++) tab[min(list[q] & 0x7Fu, 99u) * kWG] = 0;
+        }
+        *delta = dl;
+        *overflow = ovf;
+        *marked = mk_any;
+        return opens == 0;
+    }
+
     struct ParseState {
         uint32_t V[LK];  // (cost + 1) << 5 of the next LK positions, in rotating slots
         uint32_t s;      // automaton state after the current byte
@@ -549,7 +658,9 @@ struct Compressor {
                 nw = *(const uint4*)(wa + 16);
             }
             const uint32_t i = (uint32_t)(ad - wa);
-            const uint32_t w = i < 8 ? (i < 4 ? cw.x : cw.y) : (i < 12 ? cw.z : cw.w);
+            // values, not fields: a choice between fields would keep the window in memory
+            const uint32_t x = cw.x, y = cw.y, z = cw.z, u = cw.w;
+            const uint32_t w = i < 8 ? (i < 4 ? x : y) : (i < 12 ? z : u);
             return (w >> (8 * (i & 3))) & 0xFFu;
         }
     };
@@ -763,11 +874,19 @@ struct Compressor {
             bool overflow = false, malformed = false, run_rings = false;
             int delta = 0;
             const uint32_t line = b0 + st.j;
+            // the label list sits in PRE under the line (PRE is written only after the ring pass)
             uint16_t* list = (uint16_t*)pre + ((st.R + 1) >> 1);
+            uint32_t* list32 = (uint32_t*)pre + ((st.R + 3) >> 2);
             uint32_t nlab = 0;
             if (st.in && !st.bad) {
                 bool corrupt, over, pct;
-                scan_labels(raw, st.R, st.len, list, st.len >> 1, &nlab, &corrupt, &malformed, &over, &pct);
+                if constexpr (GL) {
+                    const uint32_t c32 = (st.R + st.len) >> 2, s32 = (st.R + 3) >> 2;
+                    scan_labels(raw, st.R, st.len, list32, c32 > s32 ? c32 - s32 : 0u, &nlab, &corrupt, &malformed,
+                                &over, &pct);
+                } else {
+                    scan_labels(raw, st.R, st.len, list, st.len >> 1, &nlab, &corrupt, &malformed, &over, &pct);
+                }
                 if (corrupt) {
                     st.bad = true;
                     note_error(A.ws, line_id(k0, line), kErrCorrupt);
@@ -785,8 +904,9 @@ struct Compressor {
             if (run_rings) {
                 bool ok;
                 if constexpr (GL) {
-                    // long lines hold more rings open at once: one table of 32 slots
-                    ok = ring_fast<kSlotsLong, post>(raw, st.R, list, nlab, maxlab, &delta, &overflow, &marked);
+                    // long lines hold many rings open at once: the label tables
+                    static_assert(!GL || MODE == kModeCompress, "the global-memory layout only compresses");
+                    ok = ring_table(raw, st.R, list32, nlab, maxlab, &delta, &overflow, &marked);
                 } else {
                     // a table of 4 slots first (more rings than that are rarely open at
                     // once), 8 for the lines it cannot hold
@@ -828,39 +948,53 @@ struct Compressor {
         st.simple = bar_or(st.in && !st.bad && marked_lane) == 0;
         if (st.simple) st.P = st.R;
         if (!st.simple && st.in && !st.bad && st.m) {
-            uint32_t wpos = st.P;
             const uint32_t end = st.R + st.len;
-            // GL: the next two words already loaded (the stores below keep the
-            // compiler from loading ahead by itself)
-            uint32_t nw1 = 0, nw2 = 0;
             if constexpr (GL) {
-                nw1 = *(const uint32_t*)(raw + (st.R & ~3u));
-                nw2 = *(const uint32_t*)(raw + (st.R & ~3u) + 4);
-            }
-            for (uint32_t w = st.R & ~3u; w < end; w += 4) {
-                uint32_t word;
-                if constexpr (GL) {
-                    word = nw1;
-                    nw1 = nw2;
-                    nw2 = *(const uint32_t*)(raw + w + 8);
-                } else {
-                    word = *(const uint32_t*)(raw + w);
-                }
+                // 16-byte loads one chunk ahead; the line goes out as dwords (bytes
+                // only in the dwords shared with the neighbouring lines)
+                StageWriter wr;
+                wr.begin(pre, st.P);
+                const uint32_t c0 = st.R & ~15u;
+                uint4 nx = *(const uint4*)(raw + c0);
+                for (uint32_t c = c0; c < end; c += 16) {
+                    const uint4 cu = nx;
+                    nx = *(const uint4*)(raw + c + 16);  // at most 31 bytes past the line: in the buffer
+                    const uint32_t wd[4] = {cu.x, cu.y, cu.z, cu.w};
 #pragma unroll
-                for (int k = 0; k < 4; k++) {
-                    const uint32_t x = w + k;
-                    if (x >= st.R && x < end) {
-                        const uint32_t c = (word >> (8 * k)) & 0xFFu;
-                        if (c < kSkip) {
-                            pre[wpos++] = (uint8_t)c;
-                        } else if (c >= kIdMark) {
-                            const uint32_t id = c & 0x7F;
-                            if (id < 10) {
-                                pre[wpos++] = (uint8_t)('0' + id);
-                            } else {
-                                pre[wpos++] = '%';
-                                pre[wpos++] = (uint8_t)('0' + id / 10);
-                                pre[wpos++] = (uint8_t)('0' + id % 10);
+                    for (int k = 0; k < 16; k++) {
+                        const uint32_t x = c + k;
+                        const uint32_t b = (wd[k >> 2] >> (8 * (k & 3))) & 0xFFu;
+                        const uint32_t id = b & 0x7Fu;
+                        uint32_t val = b, m = 1;
+                        if (b >= kIdMark) {
+                            val = id < 10 ? '0' + id : ('%' | (('0' + id / 10) << 8) | (('0' + id % 10) << 16));
+                            m = id < 10 ? 1u : 3u;
+                        }
+                        if (b == kSkip || x < st.R || x >= end) m = 0;
+                        wr.add(m ? val : 0u, m);
+                    }
+                }
+                wr.finish();
+            } else {
+                uint32_t wpos = st.P;
+                for (uint32_t w = st.R & ~3u; w < end; w += 4) {
+                    const uint32_t word = *(const uint32_t*)(raw + w);
+#pragma unroll
+                    for (int k = 0; k < 4; k++) {
+                        const uint32_t x = w + k;
+                        if (x >= st.R && x < end) {
+                            const uint32_t c = (word >> (8 * k)) & 0xFFu;
+                            if (c < kSkip) {
+                                pre[wpos++] = (uint8_t)c;
+                            } else if (c >= kIdMark) {
+                                const uint32_t id = c & 0x7F;
+                                if (id < 10) {
+                                    pre[wpos++] = (uint8_t)('0' + id);
+                                } else {
+                                    pre[wpos++] = '%';
+                                    pre[wpos++] = (uint8_t)('0' + id / 10);
+                                    pre[wpos++] = (uint8_t)('0' + id % 10);
+                                }
                             }
                         }
                     }
@@ -1232,6 +1366,11 @@ __device__ __forceinline__ void compress_body(const CompressArgs& a) {
         uint4* dst = (uint4*)smem;
         for (uint32_t k = threadIdx.x; k < a.tab_bytes / 16; k += kWG) dst[k] = src[k];
         smem[compress_lds(a.tab_bytes, CAP, GL).ident + threadIdx.x] = (uint8_t)threadIdx.x;
+    }
+    if constexpr (GL) {
+        // the label tables of the ring IDs start empty (this thread's column)
+        uint16_t* tab = (uint16_t*)(a.glines + (uint64_t)blockIdx.x * kGlStride + kGlTab);
+        for (int v = 0; v < kLabels; v++) tab[v * kWG + threadIdx.x] = 0;
     }
     __syncthreads();
     Compressor<LK, CAP, MODE, GL> c(a, smem);

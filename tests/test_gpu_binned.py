@@ -75,6 +75,43 @@ def test_binned_edge_lines(zs, gd, odict):
     _check(zs, gd, odict, buf, off)
 
 
+def _ring_lines(seed, n):
+    """Lines of ring labels only: up to 40 rings open at once (IDs past 31), labels
+    opened and closed in either form ('5' / '%05'), repeated back to back, and
+    some lines left with rings open (malformed) between well-formed ones."""
+    rng = np.random.default_rng(seed)
+    lines = []
+    for _ in range(n):
+        parts, open_ = [], []
+        cap = int(rng.integers(1, 41))
+        for _ in range(int(rng.integers(1, 160))):
+            if rng.random() < 0.8:
+                parts.append(b"C")
+            if open_ and (len(open_) >= cap or rng.random() < 0.45):
+                v = open_.pop(int(rng.integers(0, len(open_))))
+            else:
+                free = [x for x in range(100) if x not in open_]
+                v = int(free[int(rng.integers(0, min(len(free), int(rng.integers(1, 101)))))])
+                open_.append(v)
+            parts.append(b"%d" % v if v < 10 and rng.random() < 0.8 else b"%%%02d" % v)
+        if rng.random() < 0.85:
+            while open_:
+                parts.append(b"C")
+                v = open_.pop()
+                parts.append(b"%d" % v if v < 10 and rng.random() < 0.5 else b"%%%02d" % v)
+        lines.append(b"".join(parts))
+    return lines
+
+
+def test_binned_ring_tables(zs, gd, odict):
+    """Ring IDs of the global-memory layout (label tables, latest close per ID)
+    against the oracle, over several tiles per workgroup."""
+    lines = _ring_lines(97, 3000)
+    assert max(len(x) for x in lines) <= 4096
+    buf, off = oracle.join_lines(lines)
+    _check(zs, gd, odict, buf, off, cfgs=[dict(edges=(), large_lds=(2,)), CONFIGS[4], dict(edges=())])
+
+
 def test_binned_many_tiles(zs, gd, odict):
     """The uneven mix at 60,000 lines: hundreds of tiles in each bin."""
     _check(zs, gd, odict, *smilesgen.generate("uneven", 96, 60000), cfgs=CONFIGS[1:3])
