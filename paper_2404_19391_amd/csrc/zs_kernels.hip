@@ -722,14 +722,26 @@ struct Compressor {
         }
     }
 
+    // Bytes [lo, hi) (0 <= lo, hi <= 4) of a dword as a mask.
+    __device__ static inline uint32_t byte_mask(int32_t lo, int32_t hi) {
+        lo = max(lo, 0);
+        hi = min(hi, 4);
+        if (hi <= lo) return 0u;
+        const uint32_t up = hi == 4 ? 0xFFFFFFFFu : ((1u << (8 * hi)) - 1u);
+        return up & ~((1u << (8 * lo)) - 1u);
+    }
+
     // Binned mode: copy lines [b0, b1) of the tile to RAW at their packed
     // offsets OFF - OFF[b0].  Each thread fills 16-byte pieces of RAW; the line
-    // of a piece comes from a search of OFF.  A bad line is a lone newline;
-    // a virtual final newline is not in memory.
+    // of a piece comes from a search of OFF, and each line the piece overlaps
+    // adds its bytes: from two aligned 16-byte loads shifted into place, or byte
+    // by byte where those loads would leave the input.  A bad line is a lone
+    // newline; a virtual final newline is not in memory.
     __device__ __forceinline__ void load_gather(uint32_t b0, uint32_t b1, uint8_t* raw) {
         const uint64_t* off = OFF();
         const uint64_t* abs = ABS();
         const uint32_t lo = (uint32_t)off[b0], n = (uint32_t)off[b1] - lo;
+        const uintptr_t ib = (uintptr_t)A.in, ie = ib + A.in_bytes;
         for (uint32_t r0 = threadIdx.x * 16; r0 < n; r0 += kWG * 16) {
             uint32_t l = b0, h = b1;
             while (h - l > 1) {
@@ -739,37 +751,55 @@ struct Compressor {
             }
             uint32_t q = l;
             uint32_t qs = (uint32_t)off[q] - lo, qe = (uint32_t)off[q + 1] - lo;
-            uint8_t v[16];
+            const uint32_t pe = min(r0 + 16, n);  // end of the piece's bytes
+            uint32_t w[4] = {0, 0, 0, 0};
+            while (true) {
+                // bytes [s0, s1) of the piece come from line q
+                const uint32_t s0 = max(qs, r0), s1 = min(qe, pe);
+                const uint64_t a = abs[q];
+                const bool bad = (a & kAbsBad) != 0;
+                const uint64_t src = a & ~kAbsBad;
+                const uintptr_t sa = ib + src + (s0 - qs);
+                const uintptr_t c0 = sa & ~(uintptr_t)15;
+                if (!bad && c0 >= ib && c0 + 32 <= ie) {
+                    // (the newline of such a line is in memory: a virtual one would lie past ie)
+                    const uint4 x = *(const uint4*)c0, y = *(const uint4*)(c0 + 16);
+                    // piece byte k is byte k + e of 16 zero bytes, then x, then y
+                    const uint32_t e = (uint32_t)(sa - c0) + 16u - (s0 - r0);
+                    const uint32_t z[12] = {0u, 0u, 0u, 0u, x.x, x.y, x.z, x.w, y.x, y.y, y.z, y.w};
+                    const uint32_t qd = e >> 2, rb = e & 3u;
+                    uint32_t d[5];
 #pragma unroll
-            for (int k = 0; k < 16; k++) {
-                const uint32_t r = r0 + k;
-                v[k] = 0;
-                if (r < n) {
-                    while (r >= qe) {
-                        q++;
-                        qs = qe;
-                        qe = (uint32_t)off[q + 1] - lo;
+                    for (int j = 0; j < 5; j++) {
+                        uint32_t v = 0;
+#pragma unroll
+                        for (int c = 0; c < 8; c++) v = qd == (uint32_t)c ? z[c + j] : v;
+                        d[j] = v;
                     }
-                    const uint64_t a = abs[q];
-                    if (r + 1 == qe && ((a & kAbsBad) || (a & ~kAbsBad) + (qe - qs) == A.in_bytes + 1)) v[k] = '\n';
-                    else if (!(a & kAbsBad)) v[k] = A.in[(a & ~kAbsBad) + (r - qs)];
-                }
-            }
-            if constexpr (GL) {
-                // global line buffer: whole pieces with one 16-byte store
-                if (r0 + 16 <= n) {
-                    uint32_t w[4];
 #pragma unroll
-                    for (int j = 0; j < 4; j++)
-                        w[j] = v[4 * j] | ((uint32_t)v[4 * j + 1] << 8) | ((uint32_t)v[4 * j + 2] << 16) |
-                               ((uint32_t)v[4 * j + 3] << 24);
-                    *(uint4*)(raw + r0) = make_uint4(w[0], w[1], w[2], w[3]);
-                    continue;
+                    for (int j = 0; j < 4; j++) {
+                        const uint32_t m = byte_mask((int32_t)(s0 - r0) - 4 * j, (int32_t)(s1 - r0) - 4 * j);
+                        w[j] |= __builtin_amdgcn_alignbyte(d[j + 1], d[j], rb) & m;
+                    }
+                } else {
+                    const bool vnl = !bad && src + (qe - qs) == A.in_bytes + 1;
+                    for (uint32_t r = s0; r < s1; r++) {
+                        uint32_t v = 0;
+                        if (r + 1 == qe && (bad || vnl)) v = '\n';
+                        else if (!bad) v = A.in[src + (r - qs)];
+                        w[(r - r0) >> 2] |= v << (8 * ((r - r0) & 3));
+                    }
                 }
+                if (qe >= pe) break;
+                q++;
+                qs = qe;
+                qe = (uint32_t)off[q + 1] - lo;
             }
-#pragma unroll
-            for (int k = 0; k < 16; k++)
-                if (r0 + k < n) raw[r0 + k] = v[k];
+            if (r0 + 16 <= n) {
+                *(uint4*)(raw + r0) = make_uint4(w[0], w[1], w[2], w[3]);
+            } else {
+                for (uint32_t k = 0; r0 + k < n; k++) raw[r0 + k] = (uint8_t)(w[k >> 2] >> (8 * (k & 3)));
+            }
         }
     }
 
@@ -1329,6 +1359,12 @@ struct Compressor {
                 pnl = nl;
                 ptotal = total;
             } else {
+                // binned: a tile whose output fits one stage window is emitted first,
+                // tile-relative into the free buffer, and copied out after the
+                // look-back, so that its predecessors have the emission's time to
+                // publish (plain launches park such tiles instead)
+                const bool early = A.out && nb == 1 && total + 16 <= (uint32_t)kSlotBytes;
+                if (early) emit(0, nl, st, 0, true);
                 if (tid < 64) {
                     const uint64_t ex = lookback_walk(A.status, t, total);
                     if (tid == 0) ((uint64_t*)misc)[6] = ex;
@@ -1339,7 +1375,9 @@ struct Compressor {
                 const bool fits = gbase + total <= A.out_cap;
                 if (A.out && !fits && tid == 0) atomicOr(&A.ws->enospc, 1u);
                 if (A.out && fits) {
-                    if (nb == 1) {
+                    if (early) {
+                        copy_slot_direct(A.out, stage, total, gbase);
+                    } else if (nb == 1) {
                         emit(0, nl, st, gbase);
                     } else {
                         uint32_t b0 = 0;
