@@ -81,7 +81,7 @@ constexpr uint32_t kBadLine = 0x8000u;  // LENS flag: the line is bad (empty out
 
 struct CompressLds {
     uint32_t tab_bytes;  // dictionary part staged
-    uint32_t raw, pre, esc, off, cost, eoff, lens, perm, misc, sink, ident, abs;
+    uint32_t raw, pre, esc, off, cost, eoff, lens, perm, misc, sink, ident, ring, abs;
     uint32_t total;         // plain mode
     uint32_t total_gather;  // binned mode (ABS at the end)
 };
@@ -102,6 +102,7 @@ __host__ __device__ inline CompressLds compress_lds(uint32_t tab_bytes, uint32_t
     L.misc = o; o += 256;
     L.sink = o; o += kCL;  // one byte per lane: stores of parse steps past the line's start
     L.ident = o; o += 256; // ident[b] = b: an escaped byte is looked up like a code
+    L.ring = o;  o += gl ? kCL * 32 : 0;  // gl: 32-byte expansion rings, one per lane, dword-interleaved
     L.total = align16(o);
     L.abs = L.total;  // only binned launches allocate it
     L.total_gather = L.abs + align16(kCL * 8);
@@ -665,10 +666,12 @@ struct Compressor {
         }
     };
 
+    // GL: the group's code bytes are collected in cw (byte j of the group, from
+    // its lowest position, in byte j % 4 of cw[j / 4]) and stored at once.
     template <int K>
     __device__ __forceinline__ void parse_steps(ParseState& ps, uint8_t* buf, uint32_t base, uint32_t m,
                                                 uint32_t top, int32_t P, uint8_t* sink, uint32_t Cs,
-                                                uint32_t* escm, const Win& win) {
+                                                uint32_t* escm, const Win& win, uint32_t* cw) {
         if constexpr (K < LK) {
             const uint32_t it = base + K;
             const bool act = it < m;
@@ -710,7 +713,11 @@ struct Compressor {
                 // one-byte code of c, or (escape) c itself
                 const uint32_t tb = (ch >= 2) ? off_code + s * LK - 1 : (ch == 1) ? off_code1 : L.ident;
                 const uint32_t t = smem[tb + ((ch >= 2) ? ch : ps.c)];
-                *(act ? buf + pos : sink) = (uint8_t)t;
+                if constexpr (GL) {
+                    cw[(LK - 1 - K) / 4] |= t << (8 * ((LK - 1 - K) % 4));
+                } else {
+                    *(act ? buf + pos : sink) = (uint8_t)t;
+                }
                 *escm |= ((act && ch == 0) ? 1u : 0u) << K;
                 ps.V[K] = act ? (Kmin | 31u) + 1u : ps.V[K];
                 ps.s = sn;
@@ -718,7 +725,7 @@ struct Compressor {
                 ps.cn = cnn;
                 ps.coln = colnn;
             }
-            parse_steps<K + 1>(ps, buf, base, m, top, P, sink, Cs, escm, win);
+            parse_steps<K + 1>(ps, buf, base, m, top, P, sink, Cs, escm, win, cw);
         }
     }
 
@@ -966,24 +973,32 @@ struct Compressor {
             marked_lane = marked;
             if (st.in && !st.bad) st.m = (prep && !malformed) ? (uint32_t)((int)st.len + delta) : st.len;
             // ---- pack the pre-processed lines (in lane order)
+            // GL: each line ends on a 16-byte boundary, its padding in front of it
             uint32_t total;
-            st.P = block_excl_scan(st.in ? st.m : 0u, misc + 4, &total);
+            const uint32_t mm = st.in ? st.m : 0u;
+            const uint32_t slot = GL ? (mm + 15u) & ~15u : mm;
+            st.P = block_excl_scan(slot, misc + 4, &total) + (slot - mm);
             if constexpr (GL) ext = max(total, (uint32_t)(off[b1] - lo) + base_off);
             if (total <= (uint32_t)kPreCap) break;
             // rare: growth made PRE overflow; redo with fewer lines
             b1 = b0 + max(1u, nb / 2);
             bar();
         }
-        // ---- expand markers into PRE (only when some line changed length)
-        st.simple = bar_or(st.in && !st.bad && marked_lane) == 0;
+        // ---- expand markers into PRE (only when some line changed length; GL:
+        //      always, into the aligned layout)
+        if constexpr (GL) st.simple = false;
+        else st.simple = bar_or(st.in && !st.bad && marked_lane) == 0;
         if (st.simple) st.P = st.R;
         if (!st.simple && st.in && !st.bad && st.m) {
             const uint32_t end = st.R + st.len;
             if constexpr (GL) {
-                // 16-byte loads one chunk ahead; the line goes out as dwords (bytes
-                // only in the dwords shared with the neighbouring lines)
-                StageWriter wr;
-                wr.begin(pre, st.P);
+                // 16-byte loads one chunk ahead.  The bytes go through a 32-byte ring of
+                // this lane in LDS (byte s of the ring in byte s % 4 of row s / 4, rows
+                // kWG dwords apart) and out as aligned 16-byte blocks, at most one per
+                // input word; the first block starts in the line's padding and the
+                // last one ends with the line.
+                uint8_t* ring = smem + L.ring + 4 * threadIdx.x;
+                uint32_t wpos = st.P, fb = st.P & ~15u;
                 const uint32_t c0 = st.R & ~15u;
                 uint4 nx = *(const uint4*)(raw + c0);
                 for (uint32_t c = c0; c < end; c += 16) {
@@ -995,16 +1010,32 @@ struct Compressor {
                         const uint32_t x = c + k;
                         const uint32_t b = (wd[k >> 2] >> (8 * (k & 3))) & 0xFFu;
                         const uint32_t id = b & 0x7Fu;
-                        uint32_t val = b, m = 1;
-                        if (b >= kIdMark) {
-                            val = id < 10 ? '0' + id : ('%' | (('0' + id / 10) << 8) | (('0' + id % 10) << 16));
-                            m = id < 10 ? 1u : 3u;
+                        const bool in = x >= st.R && x < end && b != kSkip;
+                        const bool three = b >= kIdMark && id >= 10;
+                        const uint32_t b0 = three ? '%' : (b >= kIdMark ? '0' + id : b);
+                        if (in) {
+                            const uint32_t sl = wpos & 31u;
+                            ring[(sl >> 2) * (kWG * 4) + (sl & 3u)] = (uint8_t)b0;
+                            wpos++;
+                            if (three) {
+                                const uint32_t s1 = wpos & 31u, s2 = (wpos + 1) & 31u;
+                                ring[(s1 >> 2) * (kWG * 4) + (s1 & 3u)] = (uint8_t)('0' + id / 10);
+                                ring[(s2 >> 2) * (kWG * 4) + (s2 & 3u)] = (uint8_t)('0' + id % 10);
+                                wpos += 2;
+                            }
                         }
-                        if (b == kSkip || x < st.R || x >= end) m = 0;
-                        wr.add(m ? val : 0u, m);
+                        if ((k & 3) == 3 && wpos - fb >= 16) {
+                            const uint32_t* rw = (const uint32_t*)(ring + ((fb & 16u) >> 2) * (kWG * 4));
+                            *(uint4*)(pre + fb) = make_uint4(rw[0], rw[kWG], rw[2 * kWG], rw[3 * kWG]);
+                            fb += 16;
+                        }
                     }
                 }
-                wr.finish();
+                while (fb < wpos) {  // wpos = P + m, a 16-byte boundary
+                    const uint32_t* rw = (const uint32_t*)(ring + ((fb & 16u) >> 2) * (kWG * 4));
+                    *(uint4*)(pre + fb) = make_uint4(rw[0], rw[kWG], rw[2 * kWG], rw[3 * kWG]);
+                    fb += 16;
+                }
             } else {
                 uint32_t wpos = st.P;
                 for (uint32_t w = st.R & ~3u; w < end; w += 4) {
@@ -1071,7 +1102,19 @@ struct Compressor {
                     win = nwin;
                     nwin = load_win(buf, max((int32_t)top - (int32_t)(base + LK) - LK - 1, (int32_t)st.P - LK - 2));
                 }
-                parse_steps<0>(ps, buf, base, m, top, (int32_t)st.P, sink, Cs, &escm, win);
+                uint32_t cw[LK / 4];
+#pragma unroll
+                for (int k = 0; k < LK / 4; k++) cw[k] = 0;
+                parse_steps<0>(ps, buf, base, m, top, (int32_t)st.P, sink, Cs, &escm, win, cw);
+                if constexpr (GL) {
+                    // the group's bytes end on an LK-aligned position (lines end on 16-byte
+                    // boundaries); bytes before the line's start fall in its padding
+                    if (base < m) {
+                        uint8_t* g = buf + (top - base - (LK - 1));
+                        if constexpr (LK == 8) *(uint2*)g = make_uint2(cw[0], cw[1]);
+                        else *(uint4*)g = make_uint4(cw[0], cw[1], cw[2], cw[3]);
+                    }
+                }
                 esc_any |= escm != 0;
                 for (; escm; escm &= escm - 1) {  // rare: bytes with no code of their own
                     const uint32_t pos = top - (base + (uint32_t)__builtin_ctz(escm));
