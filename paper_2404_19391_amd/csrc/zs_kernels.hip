@@ -59,10 +59,13 @@ constexpr int kCapLarge = 26624;
 // its own region of the workspace, so LDS holds only the automaton and the
 // per-line arrays and a tile of 256 long lines keeps every lane busy.
 constexpr int kCapGlobal = 262144;
-constexpr int kLabels = 100;  // ring label values 0..99
-// RAW, PRE, ESC bits, the label tables of the ring IDs (u16 per label and lane), margins
-constexpr size_t kGlStride = 2 * (size_t)kCapGlobal + kCapGlobal / 8 + 256 + (size_t)kLabels * kWG * 2;
-constexpr size_t kGlTab = 2 * (size_t)kCapGlobal + kCapGlobal / 8 + 256;  // offset of the label tables
+constexpr size_t kGlStride = 2 * (size_t)kCapGlobal + kCapGlobal / 8 + 256;  // RAW, PRE, ESC bits, margins
+// Global-memory layout: the ring pass's LDS tables, per lane: a byte per label
+// value (its open ring's slot + 1) and kOpenSlots u16 slots of open rings.  They
+// share LDS with the dictionary image, which is staged again before the parse.
+constexpr int kLabels = 100;
+constexpr int kOpenSlots = 32;
+constexpr uint32_t kRingRegion = (uint32_t)(kLabels + 2 * kOpenSlots) * 256u;
 constexpr int kSlots = 8;             // fast ring table (registers): up to 8 open rings, found by label
 constexpr int kSlotsFirst = 4;        // the smaller table tried first
 constexpr int kGenLane = 400;         // per-lane ring tables in global memory (any line):
@@ -89,7 +92,9 @@ struct CompressLds {
 __host__ __device__ inline CompressLds compress_lds(uint32_t tab_bytes, uint32_t cap, bool gl = false) {
     CompressLds L;
     L.tab_bytes = align16(tab_bytes);
-    uint32_t o = L.tab_bytes;
+    // gl: the dictionary's region also holds the ring tables, then the expansion rings
+    L.ring = 0;
+    uint32_t o = gl ? (L.tab_bytes > kRingRegion ? L.tab_bytes : kRingRegion) : L.tab_bytes;
     const uint32_t lds_cap = gl ? 0u : cap;  // gl: RAW, PRE and ESC are in global memory
     L.raw = o;  o += lds_cap;
     L.pre = o;  o += lds_cap;
@@ -102,7 +107,6 @@ __host__ __device__ inline CompressLds compress_lds(uint32_t tab_bytes, uint32_t
     L.misc = o; o += 256;
     L.sink = o; o += kCL;  // one byte per lane: stores of parse steps past the line's start
     L.ident = o; o += 256; // ident[b] = b: an escaped byte is looked up like a code
-    L.ring = o;  o += gl ? kCL * 32 : 0;  // gl: 32-byte expansion rings, one per lane, dword-interleaved
     L.total = align16(o);
     L.abs = L.total;  // only binned launches allocate it
     L.total_gather = L.abs + align16(kCL * 8);
@@ -239,7 +243,6 @@ struct Compressor {
     uint8_t* g_raw = nullptr;  // GL: this workgroup's line buffers in global memory
     uint8_t* g_pre = nullptr;
     uint32_t* g_esc = nullptr;
-    uint16_t* g_tab = nullptr;  // GL: label tables of the ring IDs, one column per lane
     const TableHeader* H;
     const uint8_t* LENT;  // expansion lengths
     const uint8_t* COL;
@@ -255,7 +258,6 @@ struct Compressor {
             g_raw = b;
             g_pre = b + CAP;
             g_esc = (uint32_t*)(b + 2 * (size_t)CAP);
-            g_tab = (uint16_t*)(a.glines + (uint64_t)blockIdx.x * kGlStride + kGlTab);
         }
         H = (const TableHeader*)smem;
         if constexpr (MODE == kModeCompress) {
@@ -331,7 +333,8 @@ struct Compressor {
     // depth, ring labels - a digit outside brackets, or '%' outside brackets
     // followed by two digits (Sec. II).  Labels go to `list`: u16 entries hold
     // the position in the line << 4 and the digit, or 15 for a '%' label; u32
-    // entries the position << 8, 0x80 for a '%' label and the label value.
+    // entries (global-memory layout: list 16-byte aligned, stored four entries
+    // at a time) the position << 8, 0x80 for a '%' label and the label value.
     __device__ static inline uint32_t eq_bytes(uint32_t w, uint32_t pat) {
         const uint32_t x = w ^ pat;
         return ~(((x & 0x7F7F7F7Fu) + 0x7F7F7F7Fu) | x) & 0x80808080u;
@@ -346,6 +349,9 @@ struct Compressor {
         uint32_t bad = 0, mal = 0, pct_any = 0;
         bool over = false;
         const uint32_t end = R + len;
+        uint32_t grp[8];  // u32 entries: the last two groups of four
+#pragma unroll
+        for (int i = 0; i < 8; i++) grp[i] = 0;
         // one word: w its position (w < end), next the word after it
         auto step = [&](uint32_t w, uint32_t word, uint32_t next) __attribute__((always_inline)) {
             // flag bits of the bytes of this word that belong to the line
@@ -382,6 +388,7 @@ struct Compressor {
             carry = (uint32_t)(need >> 32);
             pct_any |= pco;
             const uint32_t lab = ((dig & ~inside & ~consumed) | pco) & 0x80808080u;
+            const uint32_t n0 = nlab;
             if (lab) {
 #pragma unroll
                 for (int k = 0; k < 4; k++) {
@@ -398,10 +405,24 @@ struct Compressor {
                             ent = ((w + k - R) << 8) |
                                   ((cb == '%') ? (0x80u | (((d1 - '0') * 10u + (d2 - '0')) & 0x7Fu)) : cb - '0');
                         }
-                        if (nlab < cap) list[nlab] = (E)ent;
-                        else over = true;
+                        if constexpr (sizeof(E) == 2) {
+                            if (nlab < cap) list[nlab] = (E)ent;
+                            else over = true;
+                        } else {
+#pragma unroll
+                            for (int i = 0; i < 8; i++) grp[i] = ((nlab & 7u) == (uint32_t)i) ? ent : grp[i];
+                        }
                         nlab++;
                     }
+                }
+            }
+            if constexpr (sizeof(E) == 4) {
+                // a word completes at most one group
+                const uint32_t g = n0 >> 2;
+                if ((nlab >> 2) != g && 4 * g + 4 <= cap) {
+                    const bool hi = (g & 1u) != 0;
+                    *(uint4*)(list + 4 * g) = hi ? make_uint4(grp[4], grp[5], grp[6], grp[7])
+                                                 : make_uint4(grp[0], grp[1], grp[2], grp[3]);
                 }
             }
         };
@@ -419,6 +440,13 @@ struct Compressor {
                 cu = nx;
                 nx = n2;
             }
+            const uint32_t g = nlab >> 2;
+            if ((nlab & 3u) && 4 * g + 4 <= cap) {  // the last, partial group
+                const bool hi = (g & 1u) != 0;
+                *(uint4*)(list + 4 * g) = hi ? make_uint4(grp[4], grp[5], grp[6], grp[7])
+                                             : make_uint4(grp[0], grp[1], grp[2], grp[3]);
+            }
+            over = nlab > cap;
         } else {
             const uint32_t w0 = R & ~3u;
             // two words in flight ahead of the one being classified
@@ -537,71 +565,82 @@ struct Compressor {
 
     // Ring IDs of the global-memory layout (long lines, many rings open at once):
     // the rule of Sec. IV-A as "latest close per ID", like ring_general, from
-    // the u32 label list.  The open ring of label v sits in this lane's column
-    // of the label table (entry v: opening position + 1, 0x8000 for a '%'
-    // label, 0 when closed; all zero between lines), the latest closing
-    // position of IDs 0..31 in registers.  The table entry of the next label is
-    // loaded one step ahead and taken from this step when the label repeats.
-    // Sets *overflow when an ID reaches 32 (the caller restores the line and
-    // takes ring_general); returns false when rings stay open.  Either way the
-    // table is cleared again.
+    // the u32 label list (16-byte aligned, read four entries at a time).  In LDS,
+    // per lane: the label byte of value v holds its open ring's slot + 1 (0 when
+    // closed; cleared by the caller), a slot the opening position + 1 and 0x8000
+    // for a '%' label; in registers the free slots and the latest closing
+    // position of IDs 0..31.  A closing writes one byte at each of the two
+    // labels: the new digit when a one-byte label stays one byte, else a marker
+    // 0x80 | id with 0x40 set when the label was a '%' label (the expansion then
+    // drops its two digits).  Sets *overflow when more than kOpenSlots rings are
+    // open or an ID reaches 32 (the caller restores the line and takes
+    // ring_general); returns false when rings stay open.
     __device__ __forceinline__ bool ring_table(uint8_t* raw, uint32_t R, const uint32_t* list, uint32_t nlab,
                                                uint32_t maxlab, int* delta, bool* overflow, bool* marked) {
-        uint16_t* tab = g_tab + threadIdx.x;  // entry v at tab[v * kWG]
-        uint32_t lct[32];                     // closing position + 1 of the latest ring that took ID k; 0: none
+        uint8_t* tab = smem + L.ring + threadIdx.x;                                      // label v at tab[v * kWG]
+        uint16_t* slots = (uint16_t*)(smem + L.ring + kLabels * kWG) + threadIdx.x;  // slot k at slots[k * kWG]
+        uint32_t used = 0;  // open slots
+        uint32_t lct[32];   // closing position + 1 of the latest ring that took ID k; 0: none
 #pragma unroll
         for (int k = 0; k < 32; k++) lct[k] = 0;
         bool mk_any = false, ovf = false;
         int dl = 0, opens = 0;
-        uint32_t e0 = list[0], e1 = list[1];  // entries past the end: unused bytes of PRE, never processed
-        uint32_t t0 = tab[min(e0 & 0x7Fu, 99u) * kWG];
-        for (uint32_t q = 0; q < maxlab; q++) {
-            const uint32_t ent = e0, cur = t0;
-            const uint32_t v = min(ent & 0x7Fu, 99u);
-            e0 = e1;
-            e1 = list[q + 2];
-            const uint32_t vn = min(e0 & 0x7Fu, 99u);
-            t0 = tab[vn * kWG];
-            uint32_t nv = cur;
-            if (q < nlab && !ovf) {
-                const uint32_t p = ent >> 8;
-                const uint32_t tl = (ent & 0x80u) ? 3u : 1u;
-                if (cur == 0) {
-                    nv = (p + 1) | (tl == 3 ? 0x8000u : 0u);
-                    opens++;
-                } else {
-                    const uint32_t o = (cur & 0x7FFFu) - 1;
-                    // IDs taken by a ring that closed after this one opened
-                    uint32_t M = 0;
-#pragma unroll
-                    for (int k = 31; k >= 0; k--) M = (M << 1) | (lct[k] > o + 1 ? 1u : 0u);
-                    if (M == 0xFFFFFFFFu) {
-                        ovf = true;
-                    } else {
-                        const uint32_t id = (uint32_t)__builtin_ctz(~M);
-#pragma unroll
-                        for (int k = 0; k < 32; k++) lct[k] = ((uint32_t)k == id) ? p + 1 : lct[k];
-                        nv = 0;
-                        opens--;
-                        const uint32_t to = (cur & 0x8000u) ? 3u : 1u;
-                        const int nlen = id < 10 ? 1 : 3;
-                        // a one-byte label that stays one byte takes its new digit in place;
-                        // anything else is marked for the expansion pass
-                        const uint8_t nb = (nlen == 1) ? (uint8_t)('0' + id) : (uint8_t)(kIdMark | id);
-                        raw[R + o] = (to == 1) ? nb : (uint8_t)(kIdMark | id);
-                        if (to == 3) raw[R + o + 1] = raw[R + o + 2] = kSkip;
-                        raw[R + p] = (tl == 1) ? nb : (uint8_t)(kIdMark | id);
-                        if (tl == 3) raw[R + p + 1] = raw[R + p + 2] = kSkip;
-                        mk_any |= (nlen != 1) | (to != 1) | (tl != 1);
-                        dl += (nlen - (int)to) + (nlen - (int)tl);
-                    }
+        auto label = [&](uint32_t ent, uint32_t q) __attribute__((always_inline)) {
+            if (q >= nlab || ovf) return;
+            const uint32_t v = min(ent & 0x7Fu, (uint32_t)kLabels - 1);
+            const uint32_t p = (ent >> 8) & 0xFFFu;
+            const uint32_t tl = (ent & 0x80u) ? 3u : 1u;
+            const uint32_t t = tab[v * kWG];
+            if (t == 0) {
+                if (used == 0xFFFFFFFFu) {
+                    ovf = true;
+                    return;
                 }
-                if (nv != cur) tab[v * kWG] = (uint16_t)nv;
+                const uint32_t k = (uint32_t)__builtin_ctz(~used);
+                used |= 1u << k;
+                slots[k * kWG] = (uint16_t)((p + 1) | (tl == 3 ? 0x8000u : 0u));
+                tab[v * kWG] = (uint8_t)(k + 1);
+                opens++;
+                return;
             }
-            if (vn == v) t0 = nv;  // loaded before this step's store
-        }
-        if (ovf || opens != 0) {
-            for (uint32_t q = 0; q < nlab; q++) tab[min(list[q] & 0x7Fu, 99u) * kWG] = 0;
+            const uint32_t cur = slots[(t - 1) * kWG];
+            const uint32_t o = (cur & 0x7FFFu) - 1;
+            // IDs taken by a ring that closed after this one opened
+            uint32_t M = 0;
+#pragma unroll
+            for (int k = 31; k >= 0; k--) M = (M << 1) | (lct[k] > o + 1 ? 1u : 0u);
+            if (M == 0xFFFFFFFFu) {
+                ovf = true;
+                return;
+            }
+            const uint32_t id = (uint32_t)__builtin_ctz(~M);
+#pragma unroll
+            for (int k = 0; k < 32; k++) lct[k] = ((uint32_t)k == id) ? p + 1 : lct[k];
+            used &= ~(1u << (t - 1));
+            tab[v * kWG] = 0;
+            opens--;
+            const uint32_t to = (cur & 0x8000u) ? 3u : 1u;
+            const int nlen = id < 10 ? 1 : 3;
+            raw[R + o] = (to == 1 && nlen == 1) ? (uint8_t)('0' + id) : (uint8_t)(kIdMark | (to == 3 ? 0x40u : 0u) | id);
+            raw[R + p] = (tl == 1 && nlen == 1) ? (uint8_t)('0' + id) : (uint8_t)(kIdMark | (tl == 3 ? 0x40u : 0u) | id);
+            mk_any |= (nlen != 1) | (to != 1) | (tl != 1);
+            dl += (nlen - (int)to) + (nlen - (int)tl);
+        };
+        // two groups of four entries in flight; a group is reloaded right after its use
+        const uint4* l4 = (const uint4*)list;  // entries past the end: unused bytes of PRE, never processed
+        uint4 ga = l4[0], gb = l4[1];
+        for (uint32_t q0 = 0; q0 < maxlab; q0 += 8) {
+            label(ga.x, q0);
+            label(ga.y, q0 + 1);
+            label(ga.z, q0 + 2);
+            label(ga.w, q0 + 3);
+            ga = l4[(q0 >> 2) + 2];
+            if (q0 + 4 >= maxlab) break;
+            label(gb.x, q0 + 4);
+            label(gb.y, q0 + 5);
+            label(gb.z, q0 + 6);
+            label(gb.w, q0 + 7);
+            gb = l4[(q0 >> 2) + 3];
         }
         *delta = dl;
         *overflow = ovf;
@@ -823,6 +862,12 @@ struct Compressor {
         const uint32_t tid = threadIdx.x;
         const bool prep = (A.flags & ZS_F_PREPROCESS) != 0;
         // ---- extent of the batch
+        if constexpr (GL) {
+            // the label bytes of the ring tables start at zero (the dictionary's
+            // LDS, free until the parse; the barriers below order this)
+            for (uint32_t k = tid; k < (uint32_t)kLabels * kWG / 16; k += kWG)
+                ((uint4*)(smem + L.ring))[k] = make_uint4(0, 0, 0, 0);
+        }
         if (tid == 0) misc[0] = nl;
         bar();
         {
@@ -836,6 +881,7 @@ struct Compressor {
         uint32_t b1 = misc[0];
         bar();
         bool marked_lane = false;
+        bool gen_lane = false;  // the line's markers are ring_general's (GL expansion)
         uint32_t ext = 0;  // bytes of RAW or PRE the batch uses (GL: the escape bits cleared)
         while (true) {
             const uint32_t nb = b1 - b0;
@@ -913,13 +959,13 @@ struct Compressor {
             const uint32_t line = b0 + st.j;
             // the label list sits in PRE under the line (PRE is written only after the ring pass)
             uint16_t* list = (uint16_t*)pre + ((st.R + 1) >> 1);
-            uint32_t* list32 = (uint32_t*)pre + ((st.R + 3) >> 2);
+            uint32_t* list32 = (uint32_t*)(pre + ((st.R + 15) & ~15u));
             uint32_t nlab = 0;
             if (st.in && !st.bad) {
                 bool corrupt, over, pct;
                 if constexpr (GL) {
-                    const uint32_t c32 = (st.R + st.len) >> 2, s32 = (st.R + 3) >> 2;
-                    scan_labels(raw, st.R, st.len, list32, c32 > s32 ? c32 - s32 : 0u, &nlab, &corrupt, &malformed,
+                    const uint32_t le = (st.R + st.len) & ~15u, ls = (st.R + 15) & ~15u;
+                    scan_labels(raw, st.R, st.len, list32, le > ls ? (le - ls) / 4 : 0u, &nlab, &corrupt, &malformed,
                                 &over, &pct);
                 } else {
                     scan_labels(raw, st.R, st.len, list, st.len >> 1, &nlab, &corrupt, &malformed, &over, &pct);
@@ -967,9 +1013,10 @@ struct Compressor {
                     restore_line(raw, st.R, line_src(line), st.len);
                 } else {
                     marked = true;
+                    gen_lane = true;
                 }
             }
-            if (malformed) marked = false;  // restored: the raw bytes are the line
+            if (malformed) marked = gen_lane = false;  // restored: the raw bytes are the line
             marked_lane = marked;
             if (st.in && !st.bad) st.m = (prep && !malformed) ? (uint32_t)((int)st.len + delta) : st.len;
             // ---- pack the pre-processed lines (in lane order)
@@ -1001,6 +1048,11 @@ struct Compressor {
                 uint32_t wpos = st.P, fb = st.P & ~15u;
                 const uint32_t c0 = st.R & ~15u;
                 uint4 nx = *(const uint4*)(raw + c0);
+                // markers: ring_general's drop a byte (kSkip) or carry an ID below 100;
+                // the label tables' carry an ID below 32, with 0x40 when the two digits
+                // of a '%' label follow (dropped here)
+                const uint32_t idm = gen_lane ? 0x7Fu : 0x3Fu;
+                uint32_t sk = 0;  // digits still to drop
                 for (uint32_t c = c0; c < end; c += 16) {
                     const uint4 cu = nx;
                     nx = *(const uint4*)(raw + c + 16);  // at most 31 bytes past the line: in the buffer
@@ -1009,10 +1061,13 @@ struct Compressor {
                     for (int k = 0; k < 16; k++) {
                         const uint32_t x = c + k;
                         const uint32_t b = (wd[k >> 2] >> (8 * (k & 3))) & 0xFFu;
-                        const uint32_t id = b & 0x7Fu;
-                        const bool in = x >= st.R && x < end && b != kSkip;
-                        const bool three = b >= kIdMark && id >= 10;
-                        const uint32_t b0 = three ? '%' : (b >= kIdMark ? '0' + id : b);
+                        const bool mark = b >= kIdMark;
+                        const uint32_t id = b & idm;
+                        const bool inr = x >= st.R && x < end;
+                        const bool in = inr && b != kSkip && sk == 0;
+                        if (inr) sk = sk ? sk - 1 : ((!gen_lane && mark && (b & 0x40u)) ? 2u : 0u);
+                        const bool three = mark && id >= 10;
+                        const uint32_t b0 = three ? '%' : (mark ? '0' + id : b);
                         if (in) {
                             const uint32_t sl = wpos & 31u;
                             ring[(sl >> 2) * (kWG * 4) + (sl & 3u)] = (uint8_t)b0;
@@ -1066,6 +1121,11 @@ struct Compressor {
             uint32_t* esc = ESC();
             const uint32_t words = GL ? min((ext + 32u) / 32u, (uint32_t)kPreCap / 32u) : (uint32_t)kPreCap / 32u;
             for (uint32_t k = tid; k < words; k += kWG) esc[k] = 0;
+        }
+        if constexpr (GL) {
+            // the dictionary back into its LDS, once every lane is past the expansion
+            bar();
+            for (uint32_t k = tid; k < L.tab_bytes / 16; k += kWG) ((uint4*)smem)[k] = ((const uint4*)A.tables)[k];
         }
         bar();
         // ---- parse (backward): automaton + (min,+) window over the next LK costs
@@ -1447,11 +1507,6 @@ __device__ __forceinline__ void compress_body(const CompressArgs& a) {
         uint4* dst = (uint4*)smem;
         for (uint32_t k = threadIdx.x; k < a.tab_bytes / 16; k += kWG) dst[k] = src[k];
         smem[compress_lds(a.tab_bytes, CAP, GL).ident + threadIdx.x] = (uint8_t)threadIdx.x;
-    }
-    if constexpr (GL) {
-        // the label tables of the ring IDs start empty (this thread's column)
-        uint16_t* tab = (uint16_t*)(a.glines + (uint64_t)blockIdx.x * kGlStride + kGlTab);
-        for (int v = 0; v < kLabels; v++) tab[v * kWG + threadIdx.x] = 0;
     }
     __syncthreads();
     Compressor<LK, CAP, MODE, GL> c(a, smem);
@@ -3006,6 +3061,7 @@ zs_status zs_dict_create(const uint8_t* len, const uint8_t* exp, zs_dict** out) 
     const int ls = (int)compress_lds(d->comp_bytes, kCapSmall).total;
     const int lg = (int)compress_lds(d->comp_bytes, kCapGather).total_gather;
     const int ll = (int)compress_lds(d->comp_bytes, kCapLarge).total_gather;
+    const int lgl = (int)compress_lds(d->comp_bytes, kCapGlobal, true).total_gather;
     if (hipFuncSetAttribute((const void*)compress_kernel<8, kCapSmall>, hipFuncAttributeMaxDynamicSharedMemorySize,
                             ls) != hipSuccess ||
         hipFuncSetAttribute((const void*)compress_kernel<16, kCapSmall>, hipFuncAttributeMaxDynamicSharedMemorySize,
@@ -3018,6 +3074,10 @@ zs_status zs_dict_create(const uint8_t* len, const uint8_t* exp, zs_dict** out) 
                             ll) != hipSuccess ||
         hipFuncSetAttribute((const void*)compress_kernel<16, kCapLarge>, hipFuncAttributeMaxDynamicSharedMemorySize,
                             ll) != hipSuccess ||
+        hipFuncSetAttribute((const void*)compress_kernel_gl<8>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                            lgl) != hipSuccess ||
+        hipFuncSetAttribute((const void*)compress_kernel_gl<16>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                            lgl) != hipSuccess ||
         hipFuncSetAttribute((const void*)decompress_kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
                             (int)decompress_lds().total) != hipSuccess) {
         (void)hipFree(d->d_tables);
