@@ -84,7 +84,7 @@ constexpr uint32_t kBadLine = 0x8000u;  // LENS flag: the line is bad (empty out
 
 struct CompressLds {
     uint32_t tab_bytes;  // dictionary part staged
-    uint32_t raw, pre, esc, off, cost, eoff, lens, perm, misc, sink, ident, ring, abs;
+    uint32_t raw, pre, esc, off, cost, eoff, lens, perm, misc, sink, ident, ring, eri, abs;
     uint32_t total;         // plain mode
     uint32_t total_gather;  // binned mode (ABS at the end)
 };
@@ -92,9 +92,12 @@ struct CompressLds {
 __host__ __device__ inline CompressLds compress_lds(uint32_t tab_bytes, uint32_t cap, bool gl = false) {
     CompressLds L;
     L.tab_bytes = align16(tab_bytes);
-    // gl: the dictionary's region also holds the ring tables, then the expansion rings
+    // gl: the dictionary's region also holds the ring tables, then the expansion
+    // rings; the emission rings follow the dictionary
     L.ring = 0;
-    uint32_t o = gl ? (L.tab_bytes > kRingRegion ? L.tab_bytes : kRingRegion) : L.tab_bytes;
+    L.eri = L.tab_bytes;
+    const uint32_t gl_region = L.tab_bytes + kCL * 32 > kRingRegion ? L.tab_bytes + kCL * 32 : kRingRegion;
+    uint32_t o = gl ? gl_region : L.tab_bytes;
     const uint32_t lds_cap = gl ? 0u : cap;  // gl: RAW, PRE and ESC are in global memory
     L.raw = o;  o += lds_cap;
     L.pre = o;  o += lds_cap;
@@ -349,9 +352,9 @@ struct Compressor {
         uint32_t bad = 0, mal = 0, pct_any = 0;
         bool over = false;
         const uint32_t end = R + len;
-        uint32_t grp[8];  // u32 entries: the last two groups of four
-#pragma unroll
-        for (int i = 0; i < 8; i++) grp[i] = 0;
+        // u32 entries: queued in LDS (16 per lane, dword-interleaved, in the ring
+        // tables' slot area: the caller's barrier ends every scan before any ring pass)
+        uint32_t* eq = (uint32_t*)(smem + L.ring + kLabels * kWG) + threadIdx.x;
         // one word: w its position (w < end), next the word after it
         auto step = [&](uint32_t w, uint32_t word, uint32_t next) __attribute__((always_inline)) {
             // flag bits of the bytes of this word that belong to the line
@@ -409,8 +412,7 @@ struct Compressor {
                             if (nlab < cap) list[nlab] = (E)ent;
                             else over = true;
                         } else {
-#pragma unroll
-                            for (int i = 0; i < 8; i++) grp[i] = ((nlab & 7u) == (uint32_t)i) ? ent : grp[i];
+                            eq[(nlab & 15u) * kWG] = ent;
                         }
                         nlab++;
                     }
@@ -420,9 +422,8 @@ struct Compressor {
                 // a word completes at most one group
                 const uint32_t g = n0 >> 2;
                 if ((nlab >> 2) != g && 4 * g + 4 <= cap) {
-                    const bool hi = (g & 1u) != 0;
-                    *(uint4*)(list + 4 * g) = hi ? make_uint4(grp[4], grp[5], grp[6], grp[7])
-                                                 : make_uint4(grp[0], grp[1], grp[2], grp[3]);
+                    const uint32_t* e4 = eq + ((4 * g) & 15u) * kWG;
+                    *(uint4*)(list + 4 * g) = make_uint4(e4[0], e4[kWG], e4[2 * kWG], e4[3 * kWG]);
                 }
             }
         };
@@ -442,9 +443,8 @@ struct Compressor {
             }
             const uint32_t g = nlab >> 2;
             if ((nlab & 3u) && 4 * g + 4 <= cap) {  // the last, partial group
-                const bool hi = (g & 1u) != 0;
-                *(uint4*)(list + 4 * g) = hi ? make_uint4(grp[4], grp[5], grp[6], grp[7])
-                                             : make_uint4(grp[0], grp[1], grp[2], grp[3]);
+                const uint32_t* e4 = eq + ((4 * g) & 15u) * kWG;
+                *(uint4*)(list + 4 * g) = make_uint4(e4[0], e4[kWG], e4[2 * kWG], e4[3 * kWG]);
             }
             over = nlab > cap;
         } else {
@@ -978,6 +978,8 @@ struct Compressor {
                     else run_rings = true;
                 }
             }
+            // GL: the scan's entry queues share LDS with other lanes' ring slots
+            if constexpr (GL) bar();
             // the label loop runs to the wave's longest list (all lanes take part in the max)
             uint32_t maxlab = run_rings ? nlab : 0u;
 #pragma unroll
@@ -1219,7 +1221,58 @@ struct Compressor {
             // (codes, escapes, newline) with dword stores
             const uintptr_t a0 = rel ? 0 : (((uintptr_t)(A.out + gb0)) & ~(uintptr_t)15);
             const uintptr_t sbase = rel ? 0 : (uintptr_t)A.out - a0;
-            if constexpr (MODE != kModeCompress) {
+            if constexpr (GL && MODE == kModeCompress) {
+                if (st.in) {
+                    // the bytes go through a 32-byte ring of this lane in LDS (after the
+                    // dictionary) and out as aligned 16-byte blocks, at most one every
+                    // four codes; blocks shared with the neighbouring lines byte by byte
+                    uint8_t* rg = smem + L.eri + 4 * threadIdx.x;
+                    const uint32_t s0 = (uint32_t)(sbase + oc);
+                    uint32_t wp = s0, fb = s0 & ~15u, n = 0;
+                    auto putb = [&](uint32_t b) __attribute__((always_inline)) {
+                        const uint32_t sl = wp & 31u;
+                        rg[(sl >> 2) * (kWG * 4) + (sl & 3u)] = (uint8_t)b;
+                        wp++;
+                    };
+                    auto flush = [&](uint32_t hi) __attribute__((always_inline)) {
+                        const uint8_t* rb = rg + ((fb & 16u) >> 2) * (kWG * 4);
+                        if (fb >= s0 && hi == fb + 16) {
+                            const uint32_t* rw = (const uint32_t*)rb;
+                            *(uint4*)(stage + fb) = make_uint4(rw[0], rw[kWG], rw[2 * kWG], rw[3 * kWG]);
+                        } else {
+                            for (uint32_t x = max(fb, s0); x < hi; x++)
+                                stage[x] = rb[((x & 15u) >> 2) * (kWG * 4) + (x & 3u)];
+                        }
+                        fb += 16;
+                    };
+                    TokWin tw;
+                    tw.init(pre + st.P);
+                    uint32_t ew = 0, ewi = ~0u;  // the escape-bit word last read
+                    while (ic < m) {
+                        const uint32_t pos = st.P + ic;
+                        const uint32_t t = tw.get(pre + pos);
+                        bool e = false;
+                        if (st.esc) {
+                            if ((pos >> 5) != ewi) {
+                                ewi = pos >> 5;
+                                ew = esc[ewi];
+                            }
+                            e = ((ew >> (pos & 31)) & 1u) != 0;
+                        }
+                        if (e) {
+                            putb(0x20);
+                            putb(t);
+                            ic += 1;
+                        } else {
+                            putb(t);
+                            ic += LENT[t];
+                        }
+                        if ((++n & 3u) == 0 && wp - fb >= 16) flush(fb + 16);
+                    }
+                    putb('\n');
+                    while (fb < wp) flush(min(fb + 16, wp));
+                }
+            } else if constexpr (MODE != kModeCompress) {
                 // relabelling only: the line's bytes and its newline
                 if (st.in) {
                     StageWriter wr;
@@ -1244,12 +1297,8 @@ struct Compressor {
                     p = 0;
                     acc = 0;
                 };
-                TokWin tw;
-                if constexpr (GL) tw.init(pre + st.P);
                 while (ic < m) {
-                    uint32_t t;
-                    if constexpr (GL) t = tw.get(pre + st.P + ic);
-                    else t = pre[st.P + ic];
+                    const uint32_t t = pre[st.P + ic];
                     acc |= t << (8 * p);
                     ic += LENT[t];
                     if (++p == 4) put();
@@ -1260,23 +1309,10 @@ struct Compressor {
             } else if (st.in) {
                 StageWriter wr;
                 wr.begin(stage, (uint32_t)(sbase + oc));
-                TokWin tw;
-                uint32_t ew = 0, ewi = ~0u;  // GL: the escape-bit word last read
-                if constexpr (GL) tw.init(pre + st.P);
                 while (ic < m) {
                     const uint32_t pos = st.P + ic;
-                    uint32_t t, eb;
-                    if constexpr (GL) {
-                        t = tw.get(pre + pos);
-                        if ((pos >> 5) != ewi) {
-                            ewi = pos >> 5;
-                            ew = esc[ewi];
-                        }
-                        eb = ew;
-                    } else {
-                        t = pre[pos];
-                        eb = esc[pos >> 5];
-                    }
+                    const uint32_t t = pre[pos];
+                    const uint32_t eb = esc[pos >> 5];
                     if ((eb >> (pos & 31)) & 1u) {
                         wr.add(0x20u | (t << 8), 2);
                         ic += 1;
