@@ -19,7 +19,8 @@ struct WsHeader {
     uint32_t pad0;
     uint64_t errkey;   // min over bad lines of (index << 3 | error kind); ~0 = none
     uint64_t total;    // total output bytes (or lines, for the index)
-    uint64_t pad[4];
+    uint64_t alloc;    // binned compression: staging bytes handed out so far
+    uint64_t pad[3];
 };
 static_assert(sizeof(WsHeader) == 64, "64-byte header");
 

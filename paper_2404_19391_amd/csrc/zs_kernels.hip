@@ -1452,7 +1452,7 @@ struct Compressor {
                 mylen = tid < nl ? COST()[tid] + 1 : 0u;
                 e = block_excl_scan(mylen, misc + 4, &total);
                 if (tid < nl) EOFF()[tid] = e;
-                if (tid == 0) publish_aggregate(A.status, t, total);
+                if (tid == 0 && !A.ids) publish_aggregate(A.status, t, total);
             }
             uint8_t* stage = st.simple ? PRE() : RAW();  // the buffer not holding this tile's tokens
             // place the pending tile
@@ -1481,7 +1481,7 @@ struct Compressor {
                 bar();
             }
             if (!have) break;
-            if (t == 0 && tid == 0) A.out_off[0] = 0;
+            if (t == 0 && tid == 0 && !A.ids) A.out_off[0] = 0;
             // Binned (gather) launches place every tile at once: parked tiles gave
             // wrong bytes there under load, a cause not yet found.
             const bool defer = nb == 1 && total + 16 <= (uint32_t)kSlotBytes && A.ids == nullptr;
@@ -1498,19 +1498,28 @@ struct Compressor {
                 pnl = nl;
                 ptotal = total;
             } else {
-                // binned: a tile whose output fits one stage window is emitted first,
-                // tile-relative into the free buffer, and copied out after the
-                // look-back, so that its predecessors have the emission's time to
-                // publish (plain launches park such tiles instead)
-                const bool early = A.out && nb == 1 && total + 16 <= (uint32_t)kSlotBytes;
+                // binned: the tile's staging space comes from a bump allocator (the
+                // placement pass reads each line's staging start and length, so the
+                // staging order is free and no tile waits on another); a tile whose
+                // output fits one stage window is emitted first, tile-relative into
+                // the free buffer, and copied out afterwards
+                const bool early = A.ids && A.out && nb == 1 && total + 16 <= (uint32_t)kSlotBytes;
                 if (early) emit(0, nl, st, 0, true);
-                if (tid < 64) {
+                if (A.ids) {
+                    if (tid == 0) ((uint64_t*)misc)[6] = atomicAdd((unsigned long long*)&A.ws->alloc,
+                                                                   (unsigned long long)total);
+                } else if (tid < 64) {
                     const uint64_t ex = lookback_walk(A.status, t, total);
                     if (tid == 0) ((uint64_t*)misc)[6] = ex;
                 }
                 bar();
                 const uint64_t gbase = ((uint64_t*)misc)[6];
-                if (tid < nl) A.out_off[k0 + tid + 1] = gbase + e + mylen;
+                if (A.ids) {
+                    // staging start << 16 | compressed length (at most ZS_MAX_CLINE + 1)
+                    if (tid < nl) A.out_off[k0 + tid] = ((gbase + e) << 16) | mylen;
+                } else if (tid < nl) {
+                    A.out_off[k0 + tid + 1] = gbase + e + mylen;
+                }
                 const bool fits = gbase + total <= A.out_cap;
                 if (A.out && !fits && tid == 0) atomicOr(&A.ws->enospc, 1u);
                 if (A.out && fits) {
@@ -2525,7 +2534,7 @@ __global__ void __launch_bounds__(kWG) bin_scatter_kernel(BinArgs a) {
 
 struct PlaceArgs {
     const uint32_t* pos_of;
-    const uint64_t* soff;   // staging offsets in bin order (n + 1 entries)
+    const uint64_t* soff;   // per line in bin order: staging start << 16 | compressed length
     const uint8_t* staging;
     uint64_t n;
     uint8_t* out;
@@ -2548,7 +2557,7 @@ __global__ void __launch_bounds__(kWG) place_count_kernel(PlaceArgs a) {
         uint32_t len = 0;
         if (k < a.n) {
             const uint32_t p = a.pos_of[k];
-            len = (uint32_t)(a.soff[p + 1] - a.soff[p]);
+            len = (uint32_t)(a.soff[p] & 0xFFFFu);
         }
         const uint32_t s = (uint32_t)wave_sum64(len);
         if (lane == 0) sc[w] = s;
@@ -2572,8 +2581,8 @@ __global__ void __launch_bounds__(kWG) place_write_kernel(PlaceArgs a) {
         uint32_t len = 0;
         if (tid < nl) {
             const uint32_t p = a.pos_of[k0 + tid];
-            src[tid] = a.soff[p];
-            len = (uint32_t)(a.soff[p + 1] - a.soff[p]);
+            src[tid] = a.soff[p] >> 16;
+            len = (uint32_t)(a.soff[p] & 0xFFFFu);
         }
         uint32_t tot;
         const uint32_t ex = block_excl_scan(len, sc, &tot);
@@ -2650,6 +2659,7 @@ __global__ void binned_init_kernel(WsHeader* h1, WsHeader* h2, BinPlan* plan, Bi
             hs[j]->enospc = 0;
             hs[j]->errkey = ~0ull;
             hs[j]->total = 0;
+            hs[j]->alloc = 0;
         }
         plan->nbins = cfg.nbins;
         if (res) {
@@ -2962,16 +2972,16 @@ size_t ws_bytes_for(int op, uint64_t n) {
 
 // Workspace of the binned compression, carved in this order.
 struct BinnedWs {
-    WsHeader* h1;      // errors, ENOSPC (all launches)
+    WsHeader* h1;      // errors, ENOSPC, the staging allocator (all launches)
     WsHeader* h2;      // the placement pass's finishing count
     BinPlan* plan;
     uint32_t* hist;    // [chunk][kMaxBins]
-    uint64_t* status;  // look-back words of the compression tiles
+    uint64_t* status;  // unused (null): binned tiles take staging space from a bump allocator
     uint8_t* gen;
     uint8_t* slots;
     uint32_t* ids;
     uint32_t* pos_of;
-    uint64_t* soff;    // staging offsets in bin order, n + 1
+    uint64_t* soff;    // per line in bin order: staging start << 16 | compressed length
     uint32_t* ptotal;  // placement tile totals
     uint64_t* pbase;   // their exclusive prefix, + 1
     uint8_t* staging;
@@ -2998,7 +3008,7 @@ BinnedWs binned_ws(void* ws, uint64_t n, uint64_t out_cap, int cus) {
     w.h2 = (WsHeader*)take(sizeof(WsHeader));
     w.plan = (BinPlan*)take(sizeof(BinPlan));
     w.hist = (uint32_t*)take((size_t)w.nchunks * kMaxBins * 4);
-    w.status = (uint64_t*)take((size_t)w.max_tiles * 8);
+    w.status = nullptr;  // binned launches take staging space from a bump allocator, no look-back
     w.gen = take(grid * kWG * kGenLane);
     w.slots = take(grid * kCapLarge);
     w.ids = (uint32_t*)take(n * 4);
@@ -3308,9 +3318,6 @@ zs_status zs_compress_binned(const zs_dict* d, const uint8_t* in, uint64_t in_by
     hipLaunchKernelGGL(bin_count_kernel, dim3(bgrid), dim3(kWG), 0, s, ba);
     hipLaunchKernelGGL(bin_plan_kernel, dim3(1), dim3(kWG), 0, s, ba);
     hipLaunchKernelGGL(bin_scatter_kernel, dim3(bgrid), dim3(kWG), 0, s, ba);
-    // zero the look-back words of every possible tile
-    hipLaunchKernelGGL(init_kernel, dim3(std::min(w.max_tiles / 256 + 1, 1024u)), dim3(256), 0, s, w.h2, w.status,
-                       w.max_tiles, (ResultOut*)nullptr);
     if (hipGetLastError() != hipSuccess) return ZS_EDEVICE;
     // one compression launch per run of bins that share an LDS layout
     CompressArgs a;
