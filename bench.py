@@ -59,7 +59,8 @@ def parse():
     ap.add_argument("--serve-plain", type=int, default=1000, help="requests replayed through the plain calls")
     ap.add_argument("--probe-copy", action="store_true",
                     help="after the timed steps, one plain 1 GiB device copy (scales the HBM byte counters)")
-    ap.add_argument("--tune-lines", type=int, default=1_000_000, help="sample the autotuner times (uneven)")
+    ap.add_argument("--tune-lines", type=int, default=1_000_000,
+                    help="sample the autotuner times (uneven); 0: no autotuning, long lines in global memory")
     return ap.parse_args()
 
 
@@ -300,8 +301,8 @@ def bench_uneven(args):
     """Uneven line lengths: 20M lines, 90% drug-like (10..120 chars) and 10% long chains
     (200..1,000 chars, deep branches, %nn ring labels), drawn independently per line.
     Compression by the plain call, by the length-binned call with a fixed configuration,
-    with the autotuned configuration, and as a replayed HIP graph of the autotuned call;
-    all four must give the same bytes."""
+    with the autotuned configuration (--tune-lines 0: long lines in global memory instead),
+    and as a replayed HIP graph of that call; all four must give the same bytes."""
     import torch
     import paper_2404_19391_amd as zs
     import smilesgen
@@ -326,12 +327,20 @@ def bench_uneven(args):
     torch.cuda.synchronize()
     ref_off = oo.clone()
     log("plain: %d -> %d bytes" % (raw, total))
-    # autotune on a sample (the first tune-lines lines)
+    # autotune on a sample (the first tune-lines lines), or a fixed configuration
     k = min(args.tune_lines, n)
-    t0 = time.perf_counter()
-    cfg_t, tuned_ms, plain_sample_ms, tried = zs.autotune_binned(d, b, o[:k + 1])
-    tune_s = time.perf_counter() - t0
-    log("autotuned on %d lines in %.1f s over %d configs: %s" % (k, tune_s, tried, cfg_t.as_dict()))
+    if k > 0:
+        t0 = time.perf_counter()
+        cfg_t, tuned_ms, plain_sample_ms, tried = zs.autotune_binned(d, b, o[:k + 1])
+        tune_s = time.perf_counter() - t0
+        log("autotuned on %d lines in %.1f s over %d configs: %s" % (k, tune_s, tried, cfg_t.as_dict()))
+        tname = "binned_autotuned"
+    else:
+        cfg_t = zs.BinConfig.make(edges=(128,), lines_per_tile=(256, 256), large_lds=(0, 2))
+        tuned_ms = plain_sample_ms = tune_s = None
+        tried = 0
+        log("no autotuning: %s" % cfg_t.as_dict())
+        tname = "binned_long_global"
     cfg_f = zs.BinConfig.make(edges=(128,), lines_per_tile=(256, 64), large_lds=(0, 1))
     ws_b = torch.empty(zs.binned_workspace_bytes(n, total), dtype=torch.uint8, device=dev)
     out_b = torch.empty(total, dtype=torch.uint8, device=dev)
@@ -339,7 +348,7 @@ def bench_uneven(args):
     runs = {
         "plain": lambda: zs.compress_into(d, b, o, out_p, oo, ws_p, res),
         "binned_fixed": lambda: zs.compress_binned_into(d, b, o, out_b, ob, cfg_f, ws_b, res),
-        "binned_autotuned": lambda: zs.compress_binned_into(d, b, o, out_b, ob, cfg_t, ws_b, res),
+        tname: lambda: zs.compress_binned_into(d, b, o, out_b, ob, cfg_t, ws_b, res),
     }
     identical = {}
     times = {}
@@ -351,7 +360,7 @@ def bench_uneven(args):
         code, fb = zs.read_result(res)
         identical[name] = bool(code == 0 and torch.equal(out_b if name != "plain" else out_p, out_p)
                                and torch.equal(ob if name != "plain" else oo, ref_off))
-    # the autotuned call as a HIP graph on a side stream
+    # that call as a HIP graph on a side stream
     s = torch.cuda.Stream(device=dev)
     g = zs.Graph()
     out_b.fill_(0)
@@ -362,8 +371,8 @@ def bench_uneven(args):
     for _ in range(args.warmup):
         g.replay(s)
     s.synchronize()
-    times["binned_autotuned_graph"] = time_ms(lambda: g.replay(s), s, args.steps)
-    identical["binned_autotuned_graph"] = bool(torch.equal(out_b, out_p) and torch.equal(ob, ref_off))
+    times[tname + "_graph"] = time_ms(lambda: g.replay(s), s, args.steps)
+    identical[tname + "_graph"] = bool(torch.equal(out_b, out_p) and torch.equal(ob, ref_off))
     med = {k: float(np.median(v)) for k, v in times.items()}
     best = min(med, key=med.get)
     per = {k: {"ms": round(v, 3), "user_GBs": round(raw / (v * 1e-3) / 1e9, 2),
@@ -391,9 +400,10 @@ def bench_uneven(args):
                      "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(alg / (med[best] * 1e-3) / 1e9 / HBM_PEAK_GBS, 4), "traffic": None},
         "compress": per,
-        "autotune": {"sample_lines": k, "configs_timed": tried, "seconds": round(tune_s, 2),
-                     "chosen": cfg_t.as_dict(), "sample_best_ms": round(tuned_ms, 3),
-                     "sample_plain_ms": round(plain_sample_ms, 3)},
+        "autotune": ({"sample_lines": k, "configs_timed": tried, "seconds": round(tune_s, 2),
+                      "chosen": cfg_t.as_dict(), "sample_best_ms": round(tuned_ms, 3),
+                      "sample_plain_ms": round(plain_sample_ms, 3)} if k > 0 else None),
+        "binned_config": cfg_t.as_dict(),
         "fixed_config": cfg_f.as_dict(),
     }
     print(json.dumps(out), flush=True)
