@@ -772,43 +772,6 @@ struct Compressor {
         }
     }
 
-    // LDS layouts: the same copy one byte at a time (each thread builds 16-byte
-    // pieces, the line of each byte from a walk of OFF).
-    __device__ __forceinline__ void load_gather_bytes(uint32_t b0, uint32_t b1, uint8_t* raw) {
-        const uint64_t* off = OFF();
-        const uint64_t* abs = ABS();
-        const uint32_t lo = (uint32_t)off[b0], n = (uint32_t)off[b1] - lo;
-        for (uint32_t r0 = threadIdx.x * 16; r0 < n; r0 += kWG * 16) {
-            uint32_t l = b0, h = b1;
-            while (h - l > 1) {
-                const uint32_t mid = (l + h) >> 1;
-                if ((uint32_t)off[mid] - lo <= r0) l = mid;
-                else h = mid;
-            }
-            uint32_t q = l;
-            uint32_t qs = (uint32_t)off[q] - lo, qe = (uint32_t)off[q + 1] - lo;
-            uint8_t v[16];
-#pragma unroll
-            for (int k = 0; k < 16; k++) {
-                const uint32_t r = r0 + k;
-                v[k] = 0;
-                if (r < n) {
-                    while (r >= qe) {
-                        q++;
-                        qs = qe;
-                        qe = (uint32_t)off[q + 1] - lo;
-                    }
-                    const uint64_t a = abs[q];
-                    if (r + 1 == qe && ((a & kAbsBad) || (a & ~kAbsBad) + (qe - qs) == A.in_bytes + 1)) v[k] = '\n';
-                    else if (!(a & kAbsBad)) v[k] = A.in[(a & ~kAbsBad) + (r - qs)];
-                }
-            }
-#pragma unroll
-            for (int k = 0; k < 16; k++)
-                if (r0 + k < n) raw[r0 + k] = v[k];
-        }
-    }
-
     // Bytes [lo, hi) (0 <= lo, hi <= 4) of a dword as a mask.
     __device__ static inline uint32_t byte_mask(int32_t lo, int32_t hi) {
         lo = max(lo, 0);
@@ -821,15 +784,10 @@ struct Compressor {
     // Binned mode: copy lines [b0, b1) of the tile to RAW at their packed
     // offsets OFF - OFF[b0].  Each thread fills 16-byte pieces of RAW; the line
     // of a piece comes from a search of OFF, and each line the piece overlaps
-    // adds its bytes (global-memory layout: from two aligned 16-byte loads
-    // shifted into place, or byte by byte where those loads would leave the
-    // input).  A bad line is a lone newline; a virtual final newline is not in
-    // memory.
+    // adds its bytes: from two aligned 16-byte loads shifted into place, or byte
+    // by byte where those loads would leave the input.  A bad line is a lone
+    // newline; a virtual final newline is not in memory.
     __device__ __forceinline__ void load_gather(uint32_t b0, uint32_t b1, uint8_t* raw) {
-        if constexpr (!GL) {
-            load_gather_bytes(b0, b1, raw);
-            return;
-        }
         const uint64_t* off = OFF();
         const uint64_t* abs = ABS();
         const uint32_t lo = (uint32_t)off[b0], n = (uint32_t)off[b1] - lo;
@@ -1546,10 +1504,10 @@ struct Compressor {
             } else {
                 // binned: the tile's staging space comes from a bump allocator (the
                 // placement pass reads each line's staging start and length, so the
-                // staging order is free and no tile waits on another).  Global-memory
-                // layout: a tile whose output fits one stage window is emitted first,
-                // tile-relative into the free buffer, and copied out afterwards
-                const bool early = GL && A.ids && A.out && nb == 1 && total + 16 <= (uint32_t)kSlotBytes;
+                // staging order is free and no tile waits on another); a tile whose
+                // output fits one stage window is emitted first, tile-relative into the
+                // free buffer, and copied out afterwards
+                const bool early = A.ids && A.out && nb == 1 && total + 16 <= (uint32_t)kSlotBytes;
                 if (early) emit(0, nl, st, 0, true);
                 if (A.ids) {
                     if (tid == 0) ((uint64_t*)misc)[6] = atomicAdd((unsigned long long*)&A.ws->alloc,
