@@ -59,8 +59,9 @@ def parse():
     ap.add_argument("--serve-plain", type=int, default=1000, help="requests replayed through the plain calls")
     ap.add_argument("--probe-copy", action="store_true",
                     help="after the timed steps, one plain 1 GiB device copy (scales the HBM byte counters)")
-    ap.add_argument("--tune-lines", type=int, default=1_000_000,
-                    help="sample the autotuner times (uneven); 0: no autotuning, long lines in global memory")
+    ap.add_argument("--tune-lines", type=int, default=0,
+                    help="sample the autotuner times (uneven, e.g. 1000000); 0: no autotuning, long lines in "
+                         "global memory")
     return ap.parse_args()
 
 
