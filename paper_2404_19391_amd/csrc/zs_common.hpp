@@ -299,6 +299,40 @@ struct StageWriter {
     }
 };
 
+// Bytes [lo, hi) (clamped to 0..4) of a dword as a mask.
+__device__ inline uint32_t dword_byte_mask(int32_t lo, int32_t hi) {
+    lo = max(lo, 0);
+    hi = min(hi, 4);
+    if (hi <= lo) return 0u;
+    const uint32_t up = hi == 4 ? 0xFFFFFFFFu : ((1u << (8 * hi)) - 1u);
+    return up & ~((1u << (8 * lo)) - 1u);
+}
+
+// OR into the 16-byte piece w its bytes [k0, k1) (0 <= k0 < k1 <= 16), taken from
+// the bytes at address sa onwards (piece byte k0 is the byte at sa): two aligned
+// 16-byte loads from sa's 16-byte boundary, shifted into place.  The caller checks
+// that both loads lie inside the buffer.
+__device__ inline void or_shifted_piece(uint32_t w[4], uintptr_t sa, uint32_t k0, uint32_t k1) {
+    const uintptr_t c0 = sa & ~(uintptr_t)15;
+    const uint4 x = *(const uint4*)c0, y = *(const uint4*)(c0 + 16);
+    // piece byte k is byte k + e of 16 zero bytes, then x, then y
+    const uint32_t e = (uint32_t)(sa - c0) + 16u - k0;
+    const uint32_t z[12] = {0u, 0u, 0u, 0u, x.x, x.y, x.z, x.w, y.x, y.y, y.z, y.w};
+    const uint32_t qd = e >> 2, rb = e & 3u;
+    uint32_t d[5];
+#pragma unroll
+    for (int j = 0; j < 5; j++) {
+        uint32_t v = 0;
+#pragma unroll
+        for (int c = 0; c < 8; c++) v = qd == (uint32_t)c ? z[c + j] : v;
+        d[j] = v;
+    }
+#pragma unroll
+    for (int j = 0; j < 4; j++)
+        w[j] |= __builtin_amdgcn_alignbyte(d[j + 1], d[j], rb) &
+                dword_byte_mask((int32_t)k0 - 4 * j, (int32_t)k1 - 4 * j);
+}
+
 // Copy total bytes from a 16-byte aligned buffer (a tile parked in its global
 // slot, or a stage in LDS) to out[base, base + total) directly: each thread
 // loads the two source chunks that one 16-byte chunk of the destination

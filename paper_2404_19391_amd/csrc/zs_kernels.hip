@@ -2540,6 +2540,7 @@ struct PlaceArgs {
     const uint32_t* pos_of;
     const uint64_t* soff;   // per line in bin order: staging start << 16 | compressed length
     const uint8_t* staging;
+    uint64_t staging_bytes;
     uint64_t n;
     uint8_t* out;
     uint64_t out_cap;
@@ -2572,8 +2573,10 @@ __global__ void __launch_bounds__(kWG) place_count_kernel(PlaceArgs a) {
 }
 
 // Offsets in input order, and the lines' bytes from the staging area: each
-// thread builds 16 bytes of the destination's 16-byte grid (the line of each
-// byte from a search of the tile's line starts) and stores them at once.
+// thread builds 16 bytes of the destination's 16-byte grid - the first line
+// from a search of the tile's line starts, each line the piece overlaps from two
+// aligned 16-byte loads of the staging copy shifted into place (byte by byte
+// where those loads would leave the staging area) - and stores them at once.
 __global__ void __launch_bounds__(kWG) place_write_kernel(PlaceArgs a) {
     __shared__ uint32_t e[kCL + 1];
     __shared__ uint64_t src[kCL];
@@ -2607,27 +2610,35 @@ __global__ void __launch_bounds__(kWG) place_write_kernel(PlaceArgs a) {
             const uintptr_t a0 = dst & ~(uintptr_t)15;
             const uint32_t lead = (uint32_t)(dst - a0);
             const uint32_t nch = (lead + tot + 15) >> 4;
+            const uintptr_t sb = (uintptr_t)a.staging, se = sb + a.staging_bytes;
             for (uint32_t c = tid; c < nch; c += kWG) {
                 const int32_t p0 = (int32_t)(c * 16) - (int32_t)lead;  // tile position of the chunk's byte 0
-                const uint32_t plo = (uint32_t)max(p0, 0);
+                const uint32_t plo = (uint32_t)max(p0, 0), phi = (uint32_t)min(p0 + 16, (int32_t)tot);
                 uint32_t l = 0, h = nl;
                 while (h - l > 1) {
                     const uint32_t mid = (l + h) >> 1;
                     if (e[mid] <= plo) l = mid;
                     else h = mid;
                 }
-                uint32_t q = l, qe = e[q + 1];
+                uint32_t q = l;
                 uint32_t wv[4] = {0, 0, 0, 0};
-#pragma unroll
-                for (int k = 0; k < 16; k++) {
-                    const int32_t p = p0 + k;
-                    if (p >= 0 && p < (int32_t)tot) {
-                        while ((uint32_t)p >= qe) {
-                            q++;
-                            qe = e[q + 1];
+                while (true) {
+                    // chunk bytes [k0, k1) are line q's bytes from tile position s0
+                    const uint32_t qs = e[q], qe = e[q + 1];
+                    const uint32_t s0 = max(qs, plo), s1 = min(qe, phi);
+                    const uint32_t k0 = (uint32_t)((int32_t)s0 - p0), k1 = (uint32_t)((int32_t)s1 - p0);
+                    const uintptr_t sa = sb + src[q] + (s0 - qs);
+                    const uintptr_t c0 = sa & ~(uintptr_t)15;
+                    if (c0 >= sb && c0 + 32 <= se) {
+                        or_shifted_piece(wv, sa, k0, k1);
+                    } else {
+                        for (uint32_t k = k0; k < k1; k++) {
+                            const uintptr_t b = sa + (k - k0);
+                            if (b < se) wv[k >> 2] |= (uint32_t)(*(const uint8_t*)b) << (8 * (k & 3));
                         }
-                        wv[k >> 2] |= (uint32_t)a.staging[src[q] + ((uint32_t)p - e[q])] << (8 * (k & 3));
                     }
+                    if (qe >= phi) break;
+                    q++;
                 }
                 uint8_t* d = (uint8_t*)(a0 + ((uintptr_t)c << 4));
                 if (p0 >= 0 && p0 + 16 <= (int32_t)tot) {
@@ -3365,6 +3376,7 @@ zs_status zs_compress_binned(const zs_dict* d, const uint8_t* in, uint64_t in_by
     pa.pos_of = w.pos_of;
     pa.soff = w.soff;
     pa.staging = w.staging;
+    pa.staging_bytes = cap + 16;  // binned_ws: the staging area holds the output's capacity + 16
     pa.n = n_lines;
     pa.out = out;
     pa.out_cap = out ? out_cap : ~0ull;
