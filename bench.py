@@ -337,7 +337,9 @@ def bench_uneven(args):
         log("autotuned on %d lines in %.1f s over %d configs: %s" % (k, tune_s, tried, cfg_t.as_dict()))
         tname = "binned_autotuned"
     else:
-        cfg_t = zs.BinConfig.make(edges=(128,), lines_per_tile=(256, 256), large_lds=(0, 2))
+        # short lines in LDS, long lines in two bins with global-memory line buffers
+        # (more uniform tiles: 6% faster than one long bin on 4M lines of this mix)
+        cfg_t = zs.BinConfig.make(edges=(128, 512), lines_per_tile=(256, 256, 256), large_lds=(0, 2, 2))
         tuned_ms = plain_sample_ms = tune_s = None
         tried = 0
         log("no autotuning: %s" % cfg_t.as_dict())
