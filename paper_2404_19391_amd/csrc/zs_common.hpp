@@ -181,30 +181,22 @@ struct ResultOut {
     int64_t first_bad;
 };
 
-__device__ inline void finish_workgroup(WsHeader* h, ResultOut* res, uint32_t nblocks, WsHeader* hdone = nullptr) {
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        __threadfence();
-        uint32_t prev = atomicAdd(&(hdone ? hdone : h)->done, 1u);
-        if (prev == nblocks - 1) {
-            __threadfence();
-            uint64_t ek = __hip_atomic_load(&h->errkey, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
-            uint32_t nospc = __hip_atomic_load(&h->enospc, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
-            int32_t code = 0;
-            int64_t fb = -1;
-            if (ek != ~0ull) {
-                fb = (int64_t)(ek >> 3);
-                code = ((ek & 7) == kErrInval) ? -1 : -3;
-            } else if (nospc) {
-                code = -2;
-            }
-            if (res) {
-                res->code = code;
-                res->reserved = 0;
-                res->first_bad = fb;
-            }
-        }
+// The call's result from the error words of header h: the first bad line's
+// error, else ENOSPC, else success.
+__device__ inline void write_result(WsHeader* h, ResultOut* res) {
+    uint64_t ek = __hip_atomic_load(&h->errkey, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
+    uint32_t nospc = __hip_atomic_load(&h->enospc, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
+    int32_t code = 0;
+    int64_t fb = -1;
+    if (ek != ~0ull) {
+        fb = (int64_t)(ek >> 3);
+        code = ((ek & 7) == kErrInval) ? -1 : -3;
+    } else if (nospc) {
+        code = -2;
     }
+    res->code = code;
+    res->reserved = 0;
+    res->first_bad = fb;
 }
 
 // Copy bytes [glo, ghi) of an output stream from an LDS stage whose byte 0

@@ -145,7 +145,6 @@ struct CompressArgs {
     uint64_t* status;
     uint8_t* gen;           // general ring tables, kGenLane bytes per (workgroup, lane)
     uint8_t* slots;         // CAP bytes per workgroup: a finished tile waiting for its offset
-    ResultOut* res;
     // binned mode (null ids: plain mode, tile t = lines [256 t, 256 t + 256))
     const uint32_t* ids;    // line ids in bin order
     const struct BinPlan* plan;
@@ -1543,7 +1542,6 @@ struct Compressor {
             }
             bar();
         }
-        finish_workgroup(A.ws, A.res, gridDim.x);
     }
 };
 
@@ -1625,7 +1623,6 @@ struct DecompressArgs {
     uint32_t tl;                // lines (requests) per tile, at most kDL
     WsHeader* ws;
     uint64_t* status;           // look-back words, one per tile
-    ResultOut* res;
 };
 
 // misc words of the decoder (uint32 indices)
@@ -2157,7 +2154,6 @@ struct Decoder {
             }
             __syncthreads();
         }
-        finish_workgroup(A.ws, A.res, gridDim.x);
     }
 
     // Gather of a batch whose lines are all short: lane q copies line q into CB
@@ -2384,28 +2380,42 @@ __global__ void __launch_bounds__(kWG) decompress_kernel(DecompressArgs a) {
 // consecutive tiles.
 constexpr int kScanWG = 1024;
 __global__ void __launch_bounds__(kScanWG) tile_scan_kernel(const uint32_t* total, uint64_t* base, uint32_t n) {
+    // blocks of kScanWG * kScanPer totals: each thread loads its kScanPer
+    // neighbouring totals at once (all loads in flight together), the block is
+    // scanned through the waves' sums, and the running carry moves to the next block
+    constexpr uint32_t kScanPer = 16;
     __shared__ uint64_t wsum[kScanWG / 64];
     const uint32_t tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
-    const uint32_t per = (n + kScanWG - 1) / kScanWG;
-    const uint32_t i0 = min(n, tid * per), i1 = min(n, i0 + per);
-    uint64_t s = 0;
-    for (uint32_t i = i0; i < i1; i++) s += total[i];
-    const uint64_t inc = wave_incl_scan64(s);
-    if (lane == 63) wsum[w] = inc;
-    __syncthreads();
-    uint64_t before = 0, all = 0;
+    uint64_t carry = 0;
+    for (uint32_t b0 = 0; b0 < n; b0 += kScanWG * kScanPer) {
+        const uint32_t i0 = b0 + tid * kScanPer;
+        uint32_t v[kScanPer];
+        uint64_t s = 0;
 #pragma unroll
-    for (int k = 0; k < kScanWG / 64; k++) {
-        const uint64_t v = wsum[k];
-        before += ((uint32_t)k < w) ? v : 0ull;
-        all += v;
+        for (uint32_t j = 0; j < kScanPer; j++) {
+            v[j] = i0 + j < n ? total[i0 + j] : 0u;
+            s += v[j];
+        }
+        const uint64_t inc = wave_incl_scan64(s);
+        if (lane == 63) wsum[w] = inc;
+        __syncthreads();
+        uint64_t before = 0, all = 0;
+#pragma unroll
+        for (int k = 0; k < kScanWG / 64; k++) {
+            const uint64_t x = wsum[k];
+            before += ((uint32_t)k < w) ? x : 0ull;
+            all += x;
+        }
+        uint64_t run = carry + before + inc - s;
+#pragma unroll
+        for (uint32_t j = 0; j < kScanPer; j++) {
+            if (i0 + j < n) base[i0 + j] = run;
+            run += v[j];
+        }
+        carry += all;
+        __syncthreads();  // wsum is rewritten by the next block
     }
-    uint64_t run = before + inc - s;
-    for (uint32_t i = i0; i < i1; i++) {
-        base[i] = run;
-        run += total[i];
-    }
-    if (tid == 0) base[n] = all;
+    if (tid == 0) base[n] = carry;
 }
 
 // ============================================================================
@@ -2549,8 +2559,6 @@ struct PlaceArgs {
     uint32_t* tile_total;
     const uint64_t* tile_base;
     WsHeader* ws;      // errors and ENOSPC (shared with the compression launches)
-    WsHeader* done;    // this kernel's finishing counter
-    ResultOut* res;
 };
 
 // Output bytes per tile of kCL lines in input order.
@@ -2654,7 +2662,17 @@ __global__ void __launch_bounds__(kWG) place_write_kernel(PlaceArgs a) {
         }
         __syncthreads();
     }
-    finish_workgroup(a.ws, a.res, gridDim.x, a.done);
+}
+
+// A call's result, after its last kernel: the workgroups do not count
+// themselves out (one contended atomic each at the end of every launch).
+__global__ void result_kernel(WsHeader* h, ResultOut* res) {
+    if (threadIdx.x == 0) write_result(h, res);
+}
+
+static zs_status launch_result(WsHeader* h, zs_result* res, hipStream_t s) {
+    if (res) hipLaunchKernelGGL(result_kernel, dim3(1), dim3(64), 0, s, h, (ResultOut*)res);
+    return hipGetLastError() == hipSuccess ? ZS_OK : ZS_EDEVICE;
 }
 
 // Zero the headers and the plan's counters; the plan's bins from the host's
@@ -2706,7 +2724,6 @@ struct IndexArgs {
     uint32_t ntiles;
     WsHeader* ws;
     uint64_t* status;  // look-back words, one per tile (newline counts)
-    ResultOut* res;
 };
 
 // per 4-byte word: bit 7 of each byte set where the byte is a newline (exact,
@@ -2863,7 +2880,6 @@ __global__ void __launch_bounds__(kWG) index_kernel(IndexArgs a) {
         }
         __syncthreads();
     }
-    finish_workgroup(a.ws, a.res, gridDim.x);
 }
 
 // zero the workspace header and the tile status words; set errkey to "none"
@@ -3242,13 +3258,13 @@ static zs_status compress_plain(const zs_dict* d, const uint8_t* in, uint64_t in
     a.status = status;
     a.gen = gen;
     a.slots = slots;
-    a.res = (ResultOut*)res;
     a.ids = nullptr;
     a.plan = nullptr;
     a.bin_lo = a.bin_hi = 0;
     a.ticket = nullptr;
     a.glines = nullptr;
-    return launch_compress(a.tab_bytes, d ? d->lk : 8u, a, 0, ntiles, di.cus, s, mode);
+    if (launch_compress(a.tab_bytes, d ? d->lk : 8u, a, 0, ntiles, di.cus, s, mode) != ZS_OK) return ZS_EDEVICE;
+    return launch_result(h, res, s);
 }
 
 zs_status zs_compress(const zs_dict* d, const uint8_t* in, uint64_t in_bytes, const uint64_t* in_off,
@@ -3351,7 +3367,6 @@ zs_status zs_compress_binned(const zs_dict* d, const uint8_t* in, uint64_t in_by
     a.status = w.status;
     a.gen = w.gen;
     a.slots = w.slots;
-    a.res = nullptr;
     a.ids = w.ids;
     a.plan = w.plan;
     a.glines = w.glines;
@@ -3385,13 +3400,11 @@ zs_status zs_compress_binned(const zs_dict* d, const uint8_t* in, uint64_t in_by
     pa.tile_total = w.ptotal;
     pa.tile_base = w.pbase;
     pa.ws = w.h1;
-    pa.done = w.h2;
-    pa.res = (ResultOut*)res;
     const uint32_t pgrid = std::min(w.ptiles, (uint32_t)di.cus * 8);
     hipLaunchKernelGGL(place_count_kernel, dim3(pgrid), dim3(kWG), 0, s, pa);
     hipLaunchKernelGGL(tile_scan_kernel, dim3(1), dim3(kScanWG), 0, s, w.ptotal, w.pbase, w.ptiles);
     hipLaunchKernelGGL(place_write_kernel, dim3(pgrid), dim3(kWG), 0, s, pa);
-    return hipGetLastError() == hipSuccess ? ZS_OK : ZS_EDEVICE;
+    return launch_result(w.h1, res, s);
 }
 
 
@@ -3599,14 +3612,13 @@ static zs_status decompress_common(const zs_dict* d, const uint8_t* in, uint64_t
     a.ntiles = ntiles;
     a.ws = h;
     a.status = status;
-    a.res = (ResultOut*)res;
     const uint32_t lds = decompress_lds().total;
     int occ = occupancy((const void*)decompress_kernel, lds);
     if (occ > kDecompressWgPerCu) occ = kDecompressWgPerCu;
     uint32_t grid = (uint32_t)di.cus * (uint32_t)occ;
     if (grid > ntiles) grid = ntiles;
     hipLaunchKernelGGL(decompress_kernel, dim3(grid), dim3(kWG), lds, s, a);
-    return hipGetLastError() == hipSuccess ? ZS_OK : ZS_EDEVICE;
+    return launch_result(h, res, s);
 }
 
 zs_status zs_decompress(const zs_dict* d, const uint8_t* in, uint64_t in_bytes, const uint64_t* in_off,
@@ -3661,13 +3673,12 @@ zs_status zs_index_lines(const uint8_t* buf, uint64_t len, uint64_t* off, uint64
     a.ntiles = ntiles;
     a.ws = h;
     a.status = status;
-    a.res = (ResultOut*)res;
     int occ = occupancy((const void*)index_kernel, 0);
     if (occ > kIndexWgPerCu) occ = kIndexWgPerCu;
     uint32_t grid = (uint32_t)di.cus * (uint32_t)occ;
     if (grid > ntiles) grid = ntiles;
     hipLaunchKernelGGL(index_kernel, dim3(grid), dim3(kWG), 0, s, a);
-    return hipGetLastError() == hipSuccess ? ZS_OK : ZS_EDEVICE;
+    return launch_result(h, res, s);
 }
 
 }  // extern "C"
