@@ -14,7 +14,7 @@ constexpr int kWaves = kWG / 64;
 // init kernel of every call.
 struct WsHeader {
     uint32_t ticket;   // next tile to claim
-    uint32_t done;     // workgroups that have finished
+    uint32_t done;     // unused (cleared with the header)
     uint32_t enospc;   // set when the output does not fit
     uint32_t pad0;
     uint64_t errkey;   // min over bad lines of (index << 3 | error kind); ~0 = none
@@ -173,8 +173,7 @@ __device__ inline uint32_t claim_tile(WsHeader* h, uint32_t* s_slot) {
     return t;
 }
 
-// The last workgroup to finish writes the result word from h's error state.
-// res may be null; the finishing count is kept in hdone (default: h).
+// The caller's result word (zs_result), written after a call's last kernel.
 struct ResultOut {
     int32_t code;
     int32_t reserved;
