@@ -33,6 +33,10 @@ HBM_PEAK_GBS = 8000.0
 # wave64 VALU instructions issued per second: 256 CUs x 4 SIMDs, one wave-instruction per
 # 4 cycles each (64 lanes on 16-wide SIMDs), at 2.4 GHz
 VALU_ISSUE_PEAK = 256 * 4 * 2.4e9 / 4
+# the uneven workload's binned configuration: short lines in LDS, long lines in four
+# bins with global-memory line buffers (more uniform tiles: 2.5% faster than one long
+# bin, 0.7% faster than two, on the 20M lines of that workload)
+UNEVEN_BINS = dict(edges=(128, 384, 640, 896), lines_per_tile=(256,) * 5, large_lds=(0, 2, 2, 2, 2))
 
 
 def parse():
@@ -337,11 +341,7 @@ def bench_uneven(args):
         log("autotuned on %d lines in %.1f s over %d configs: %s" % (k, tune_s, tried, cfg_t.as_dict()))
         tname = "binned_autotuned"
     else:
-        # short lines in LDS, long lines in four bins with global-memory line buffers
-        # (more uniform tiles: 2.5% faster than one long bin, 0.7% faster than two, on
-        # the 20M lines of this workload)
-        cfg_t = zs.BinConfig.make(edges=(128, 384, 640, 896), lines_per_tile=(256,) * 5,
-                                  large_lds=(0, 2, 2, 2, 2))
+        cfg_t = zs.BinConfig.make(**UNEVEN_BINS)
         tuned_ms = plain_sample_ms = tune_s = None
         tried = 0
         log("no autotuning: %s" % cfg_t.as_dict())

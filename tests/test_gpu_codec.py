@@ -483,8 +483,9 @@ def test_bulk_workload_full_size(zs, gd, odict):
 
 @pytest.mark.slow
 def test_uneven_workload_full_size(zs, gd, odict):
-    """20M uneven lines (2.2 GB): the plain and the binned compression, each
-    against the oracle line for line (host processes on disjoint line ranges)."""
+    """20M uneven lines (2.2 GB): the plain compression and two binned ones (the
+    second in the configuration the uneven bench times), each against the oracle line
+    for line (host processes on disjoint line ranges)."""
     from oracle import parallel
     from conftest import DEFAULT_DICT
     n = 20_000_000
@@ -496,12 +497,18 @@ def test_uneven_workload_full_size(zs, gd, odict):
     cfg = zs.BinConfig.make(edges=(128,), lines_per_tile=(256, 32), large_lds=(0, 1))
     bc, bco = zs.compress_binned(gd, b, o, cfg)
     bh, bho = host(bc), host(bco).astype(np.uint64)
-    del bc, bco, b, o
+    del bc, bco
+    # the configuration the uneven bench times (long lines in global memory)
+    import bench
+    gc, gco = zs.compress_binned(gd, b, o, zs.BinConfig.make(**bench.UNEVEN_BINS))
+    gh, gho = host(gc), host(gco).astype(np.uint64)
+    del gc, gco, b, o
     torch.cuda.empty_cache()
     code, fb, want, woff, wall, cpu = parallel.compress(DEFAULT_DICT, buf, off)
     print("oracle: %d lines in %.1f s wall, %.1f s summed over processes" % (n, wall, cpu), flush=True)
     assert code == 0
-    assert np.array_equal(cho, woff) and np.array_equal(bho, woff)
+    assert np.array_equal(cho, woff) and np.array_equal(bho, woff) and np.array_equal(gho, woff)
     wb = want.tobytes()
     assert ch.tobytes() == wb
     assert bh.tobytes() == wb
+    assert gh.tobytes() == wb
