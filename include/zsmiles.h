@@ -42,8 +42,9 @@
  *
  * Workspace: `ws` is caller-owned device scratch of at least
  * zs_workspace_bytes(op, n) bytes (n = lines, or ids for
- * zs_decompress_lines); its contents need no initialisation.  Calls that
- * share a workspace must not overlap in time.
+ * zs_decompress_lines), 256-byte aligned (as hipMalloc returns it; a null
+ * or misaligned ws is ZS_EINVAL); its contents need no initialisation.
+ * Calls that share a workspace must not overlap in time.
  *
  * Thread safety: a zs_dict is immutable after creation and may be used by
  * many streams at once.
@@ -186,7 +187,7 @@ zs_status zs_index_lines(const uint8_t *buf, uint64_t len, uint64_t *off, uint64
  * pass writes the lines back in input order.  The output (out, out_off, res)
  * is identical to zs_compress's for every input; size-only mode and ENOSPC
  * behave the same.  ws: at least zs_binned_workspace_bytes(n_lines, out_cap)
- * bytes (it holds the staging copy of the output).
+ * bytes, 256-byte aligned (it holds the staging copy of the output).
  */
 #define ZS_MAX_BINS 8
 typedef struct {

@@ -3333,6 +3333,10 @@ static zs_status launch_compress(uint32_t tab_bytes, uint32_t lk, const Compress
 
 // Plain (one launch) compression; with d null, the ring relabelling alone
 // (mode: pre- or post-processing).
+// A caller's workspace: present and 256-byte aligned (the header's 64-bit
+// atomics and the 16-byte accesses of the areas carved from it rely on it).
+static inline bool ws_ok(const void* ws) { return ws && ((uintptr_t)ws & 255u) == 0; }
+
 static zs_status compress_plain(const zs_dict* d, const uint8_t* in, uint64_t in_bytes, const uint64_t* in_off,
                                 uint64_t n_lines, uint8_t* out, uint64_t out_cap, uint64_t* out_off, uint32_t flags,
                                 void* ws, zs_result* res, hipStream_t s, int mode = kModeCompress) {
@@ -3377,7 +3381,7 @@ static zs_status compress_plain(const zs_dict* d, const uint8_t* in, uint64_t in
 zs_status zs_compress(const zs_dict* d, const uint8_t* in, uint64_t in_bytes, const uint64_t* in_off,
                       uint64_t n_lines, uint8_t* out, uint64_t out_cap, uint64_t* out_off, uint32_t flags,
                       void* ws, size_t ws_bytes, zs_result* res, void* stream) {
-    if (!d || !in_off || !out_off || !ws || (!in && in_bytes)) return ZS_EINVAL;
+    if (!d || !in_off || !out_off || !ws_ok(ws) || (!in && in_bytes)) return ZS_EINVAL;
     if (ws_bytes < zs_workspace_bytes(ZS_OP_COMPRESS, n_lines)) return ZS_EINVAL;
     if (flags & ~ZS_F_PREPROCESS) return ZS_EINVAL;
     return compress_plain(d, in, in_bytes, in_off, n_lines, out, out_cap, out_off, flags, ws, res,
@@ -3387,7 +3391,7 @@ zs_status zs_compress(const zs_dict* d, const uint8_t* in, uint64_t in_bytes, co
 zs_status zs_preprocess(const uint8_t* in, uint64_t in_bytes, const uint64_t* in_off, uint64_t n_lines,
                         uint8_t* out, uint64_t out_cap, uint64_t* out_off, void* ws, size_t ws_bytes,
                         zs_result* res, void* stream) {
-    if (!in_off || !out_off || !ws || (!in && in_bytes)) return ZS_EINVAL;
+    if (!in_off || !out_off || !ws_ok(ws) || (!in && in_bytes)) return ZS_EINVAL;
     if (ws_bytes < zs_workspace_bytes(ZS_OP_COMPRESS, n_lines)) return ZS_EINVAL;
     return compress_plain(nullptr, in, in_bytes, in_off, n_lines, out, out_cap, out_off, ZS_F_PREPROCESS, ws, res,
                           (hipStream_t)stream, kModePre);
@@ -3396,7 +3400,7 @@ zs_status zs_preprocess(const uint8_t* in, uint64_t in_bytes, const uint64_t* in
 zs_status zs_postprocess(const uint8_t* in, uint64_t in_bytes, const uint64_t* in_off, uint64_t n_lines,
                          uint8_t* out, uint64_t out_cap, uint64_t* out_off, void* ws, size_t ws_bytes,
                          zs_result* res, void* stream) {
-    if (!in_off || !out_off || !ws || (!in && in_bytes)) return ZS_EINVAL;
+    if (!in_off || !out_off || !ws_ok(ws) || (!in && in_bytes)) return ZS_EINVAL;
     if (ws_bytes < zs_workspace_bytes(ZS_OP_COMPRESS, n_lines)) return ZS_EINVAL;
     return compress_plain(nullptr, in, in_bytes, in_off, n_lines, out, out_cap, out_off, ZS_F_PREPROCESS, ws, res,
                           (hipStream_t)stream, kModePost);
@@ -3411,7 +3415,7 @@ size_t zs_binned_workspace_bytes(uint64_t n_lines, uint64_t out_cap) {
 zs_status zs_compress_binned(const zs_dict* d, const uint8_t* in, uint64_t in_bytes, const uint64_t* in_off,
                              uint64_t n_lines, uint8_t* out, uint64_t out_cap, uint64_t* out_off, uint32_t flags,
                              const zs_bin_config* cfg, void* ws, size_t ws_bytes, zs_result* res, void* stream) {
-    if (!d || !in_off || !out_off || !ws || !cfg || (!in && in_bytes)) return ZS_EINVAL;
+    if (!d || !in_off || !out_off || !ws_ok(ws) || !cfg || (!in && in_bytes)) return ZS_EINVAL;
     if (flags & ~ZS_F_PREPROCESS) return ZS_EINVAL;
     if (n_lines >= (1ull << 32)) return ZS_EINVAL;
     const uint32_t nb = cfg->nbins;
@@ -3689,7 +3693,7 @@ static zs_status decompress_common(const zs_dict* d, const uint8_t* in, uint64_t
                                    uint64_t n_lines, const uint64_t* ids, uint64_t nreq, uint8_t* out,
                                    uint64_t out_cap, uint64_t* out_off, void* ws, size_t ws_bytes, zs_result* res,
                                    void* stream, int op, bool exact_ws = false) {
-    if (!d || !in_off || !out_off || !ws || (!in && in_bytes)) return ZS_EINVAL;
+    if (!d || !in_off || !out_off || !ws_ok(ws) || (!in && in_bytes)) return ZS_EINVAL;
     if (!exact_ws && ws_bytes < zs_workspace_bytes(op, nreq)) return ZS_EINVAL;
     hipStream_t s = (hipStream_t)stream;
     if (nreq == 0) {
@@ -3760,7 +3764,7 @@ zs_status zs_decompress_lines_noalloc(const zs_dict* d, const uint8_t* in, uint6
 
 zs_status zs_index_lines(const uint8_t* buf, uint64_t len, uint64_t* off, uint64_t off_cap, uint64_t* n_lines_out,
                          void* ws, size_t ws_bytes, zs_result* res, void* stream) {
-    if ((!buf && len) || !n_lines_out || !ws || (!off && off_cap)) return ZS_EINVAL;
+    if ((!buf && len) || !n_lines_out || !ws_ok(ws) || (!off && off_cap)) return ZS_EINVAL;
     if (ws_bytes < zs_workspace_bytes(ZS_OP_INDEX, len)) return ZS_EINVAL;
     hipStream_t s = (hipStream_t)stream;
     if (len == 0) {

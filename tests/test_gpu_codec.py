@@ -512,3 +512,51 @@ def test_uneven_workload_full_size(zs, gd, odict):
     assert ch.tobytes() == wb
     assert bh.tobytes() == wb
     assert gh.tobytes() == wb
+
+
+def test_misaligned_workspace_is_rejected(zs, gd):
+    """A workspace that is not 256-byte aligned is an argument error (ZS_EINVAL) in
+    every call that takes one; the same buffer at an aligned offset works."""
+    lines = [b"CCO", b"c1ccccc1", b"CC(=O)Nc1ccc(O)cc1"]
+    buf = np.frombuffer(b"".join(l + b"\n" for l in lines), dtype=np.uint8).copy()
+    off = np.concatenate([[0], np.cumsum([len(l) + 1 for l in lines])])
+    b, o = dev(buf, off)
+    n = len(lines)
+    res = zs.new_result("cuda")
+
+    def spare(op, count):
+        return torch.empty(zs.workspace_bytes(op, count) + 512, dtype=torch.uint8, device="cuda")
+
+    c, co = zs.compress(gd, b, o)
+    out = torch.empty(c.numel(), dtype=torch.uint8, device="cuda")
+    oo = torch.empty(n + 1, dtype=torch.int64, device="cuda")
+    ws = spare(zs.OP_COMPRESS, n)
+    with pytest.raises(zs.ZsError) as e:
+        zs.compress_into(gd, b, o, out, oo, ws[8:], res)
+    assert e.value.code == zs.EINVAL
+    zs.compress_into(gd, b, o, out, oo, ws[256:], res)
+    torch.cuda.synchronize()
+    assert torch.equal(out, c) and torch.equal(oo, co)
+
+    cfg = zs.BinConfig.make(edges=(), lines_per_tile=(256,), large_lds=(0,))
+    wb = torch.empty(zs.binned_workspace_bytes(n, out.numel()) + 512, dtype=torch.uint8, device="cuda")
+    with pytest.raises(zs.ZsError) as e:
+        zs.compress_binned_into(gd, b, o, out, oo, cfg, wb[64:], res)
+    assert e.value.code == zs.EINVAL
+
+    d_out = torch.empty(buf.size, dtype=torch.uint8, device="cuda")
+    d_off = torch.empty(n + 1, dtype=torch.int64, device="cuda")
+    wd = spare(zs.OP_DECOMPRESS, n)
+    with pytest.raises(zs.ZsError) as e:
+        zs.decompress_into(gd, c, co, d_out, d_off, wd[128:], res)
+    assert e.value.code == zs.EINVAL
+    zs.decompress_into(gd, c, co, d_out, d_off, wd[512:], res)
+    ref, roff = zs.decompress(gd, c, co)  # the pre-processed lines
+    torch.cuda.synchronize()
+    assert torch.equal(d_out[:ref.numel()], ref) and torch.equal(d_off, roff)
+
+    wi = spare(zs.OP_INDEX, buf.size)
+    n_out = torch.zeros(1, dtype=torch.int64, device="cuda")
+    with pytest.raises(zs.ZsError) as e:
+        zs.index_into(b, d_off, n_out, wi[4:], res)
+    assert e.value.code == zs.EINVAL
